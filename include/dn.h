@@ -1,0 +1,225 @@
+/*
+ * dn.h — C ABI of the MI355X (gfx950) Darknet-style CNN forward library.
+ *
+ * The operation is the forward pass of the convolutional network that the
+ * paper offloads to the GPU (Darknet's detection and image-edit sample
+ * programs, Sec. 5.1.1): convolution + bias + inference batch normalisation
+ * + leaky rectifier, max pooling and residual (shortcut) layers.  The
+ * paper's contribution, hoisting CPU<->GPU copies out of every loop that does
+ * not define or use the data (Sec. 3.2), becomes the library's resident mode:
+ * weights are uploaded once at load time, the input crosses once per forward,
+ * every intermediate activation stays in a device arena, and the output
+ * crosses once.  The per-layer mode copies each layer's input, weights and
+ * output around its kernel, the naive per-loop offload that Sec. 3.2 removes.
+ *
+ * Conventions for every function:
+ *   - returns dn_status (0 = DN_OK, negative = error); never throws or aborts;
+ *     on failure dn_last_error() holds a message (thread-local).
+ *   - "device pointer" = memory on the net's / the call's GPU (hipMalloc or a
+ *     torch CUDA tensor); "host pointer" = CPU memory.  The caller owns every
+ *     pointer it passes; the library keeps none of them beyond the call except
+ *     the arena bound with dn_bind_arena (kept until rebind or destroy).
+ *   - stream arguments are hipStream_t passed as void* (NULL = null stream).
+ *     Enqueueing calls return without waiting; kernel faults surface at the
+ *     caller's next synchronisation.
+ *   - Activations on the device are NHWC with the channel count padded to
+ *     dn_channel_pad(dtype, C) (16-byte multiples); padded channels hold 0.
+ *   - Reduced precisions: BF16 (round to nearest even) and FP8 OCP e4m3
+ *     (round to nearest even, saturating at +-448, per-output-channel weight
+ *     scales, one per-tensor activation scale); every product accumulates in
+ *     FP32.  Batch-norm folding into the weights runs in FP64 on the GPU.
+ */
+#ifndef DN_H
+#define DN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dn_status {
+    DN_OK = 0,
+    DN_EINVAL = -1,        /* bad argument, shape or pointer kind */
+    DN_ENOMEM = -2,        /* allocation failed or arena too small */
+    DN_EHIP = -3,          /* a HIP runtime call failed */
+    DN_ESTATE = -4,        /* call out of order (e.g. forward before load/bind) */
+    DN_EUNSUPPORTED = -5   /* valid request the library does not implement */
+} dn_status;
+
+typedef enum dn_dtype { DN_F32 = 0, DN_BF16 = 1, DN_FP8_E4M3 = 2 } dn_dtype;
+typedef enum dn_mode { DN_MODE_RESIDENT = 0, DN_MODE_PER_LAYER = 1 } dn_mode;
+typedef enum dn_kind { DN_CONV = 0, DN_MAXPOOL = 1, DN_SHORTCUT = 2 } dn_kind;
+typedef enum dn_act { DN_ACT_LINEAR = 0, DN_ACT_LEAKY = 1 } dn_act;
+
+/* One layer of the network, in Darknet's layer vocabulary (Sec. 5.1.1).
+ *   DN_CONV:     cout, ksize (square R = S), stride, pad (zero padding),
+ *                batchnorm (1 = bias then inference BN), activation.
+ *                y = act(BN(conv(x) + bias)).
+ *   DN_MAXPOOL:  ksize = window, stride; -inf outside the input; output side
+ *                (H - 1) / stride + 1; window starts at i*stride - (ksize-1)/2.
+ *   DN_SHORTCUT: src = absolute index of an earlier layer; output =
+ *                act(previous layer's output + layer src's output), shapes equal. */
+typedef struct dn_layer_desc {
+    int kind;
+    int cout, ksize, stride, pad;
+    int batchnorm;
+    int activation;
+    int src;
+} dn_layer_desc;
+
+typedef struct dn_net_opts {
+    int in_c;            /* input channels (<= 16) */
+    int max_h, max_w;    /* largest input size the net will see */
+    int max_batch;
+    int dtype;           /* dn_dtype of activations and weights */
+    int mode;            /* dn_mode */
+    float leaky_slope;   /* 0.1 for the Darknet leaky rectifier */
+    double bn_eps;       /* batch-norm epsilon (1e-5) */
+    int use_graph;       /* 1: resident forwards are captured once per
+                            (batch, h, w, x, y, arena) into a hipGraph and replayed */
+    int device;          /* HIP device ordinal */
+} dn_net_opts;
+
+typedef struct dn_net dn_net;
+
+/* ---- network object ---------------------------------------------------- */
+
+/* Validate the layer list and build the execution plan.  `layers` is copied. */
+dn_status dn_net_create(const dn_layer_desc *layers, int n, const dn_net_opts *opts, dn_net **out);
+
+/* Free everything the library allocated for the net (NULL-safe, idempotent
+ * for distinct handles; the bound arena is the caller's and is not freed). */
+void dn_net_destroy(dn_net *net);
+
+/* Output shape (logical channels) for an input of h x w. */
+dn_status dn_net_output_shape(const dn_net *net, int h, int w, int *c, int *ho, int *wo);
+
+/* Device bytes the resident plan needs for (batch, h, w): every live
+ * activation buffer (liveness-packed, 256-byte aligned) plus split-K scratch.
+ * The per-layer mode uses the same arena as its device staging area. */
+dn_status dn_arena_bytes(const dn_net *net, int batch, int h, int w, size_t *bytes);
+
+/* Bind caller-owned device memory as the activation arena (kept until
+ * rebind/destroy; must outlive every forward enqueued with it). */
+dn_status dn_bind_arena(dn_net *net, void *dev_ptr, size_t bytes);
+
+/* Upload one conv layer's FP64 host parameters: w [cout][cin][k][k], bias
+ * [cout]; mean/var/gamma/beta [cout] or all NULL when the layer has no BN.
+ * The library copies them, folds BN in FP64 on the GPU
+ * (w' = w*g/sqrt(v+eps), b' = (b-m)*g/sqrt(v+eps) + beta), rounds to the net
+ * dtype and packs; host arrays may be freed on return.  Synchronous. */
+dn_status dn_load_weights(dn_net *net, int layer, const double *w, const double *bias,
+                          const double *mean, const double *var,
+                          const double *gamma, const double *beta);
+
+/* FP8 nets only: set the static per-tensor activation scales from a
+ * calibration input (device NCHW FP32, batch x in_c x h x w).  Runs an FP32
+ * forward on the GPU with the same folded weights, takes amax of every
+ * activation tensor, scale = amax / 448.  Synchronous. */
+dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h, int w, void *stream);
+
+/* Forward.  Resident mode: x and y are device pointers (NCHW FP32, y of
+ * dn_net_output_shape); one ingest, the conv/pool/shortcut kernels and one
+ * egress are enqueued on `stream` with no host synchronisation and no
+ * allocation (or one hipGraphLaunch when use_graph is set).
+ * Per-layer mode: x and y are host pointers; every layer's input and weights
+ * are copied host->device, its kernel runs, its output is copied back and
+ * the stream is synchronised before the next layer.
+ * Requires all conv weights loaded (DN_ESTATE), an arena of at least
+ * dn_arena_bytes (DN_ENOMEM) and, for FP8, calibration (DN_ESTATE). */
+dn_status dn_forward(dn_net *net, const void *x, int batch, int h, int w, void *y, void *stream);
+
+/* Same as dn_forward in resident mode with an explicit arena instead of the
+ * bound one, so that several forwards may be in flight on disjoint arenas
+ * (the serving loop gives each in-flight slot its own arena). */
+dn_status dn_forward_arena(dn_net *net, void *arena, size_t arena_bytes, const void *x,
+                           int batch, int h, int w, void *y, void *stream);
+
+/* Pick a tile shape (and split-K factor) for every conv of the plan for
+ * (batch, h, w) by timing the candidates on the bound arena; results are
+ * cached in the net (and in the file named by $DN_TUNE_CACHE, if set).
+ * Synchronous; overwrites arena contents. */
+dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *stream);
+
+/* Average duration in ms of one launch of the kernel(s) that compute
+ * `layer` in the resident plan for (batch, h, w), timed with hipEvents over
+ * `iters` back-to-back launches on `stream` (arena contents are used as
+ * they are).  Synchronous. */
+dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int w, int iters,
+                        void *stream, float *avg_ms);
+
+/* Description of the resident plan's kernel for conv `layer` (tile config
+ * index, split-K factor, fused pool / residual flags). */
+dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int h, int w,
+                        int *tile, int *splits, int *fused_pool, int *fused_res);
+
+/* ---- standalone layer kernels on device memory ------------------------- */
+
+int dn_channel_pad(int dtype, int c);
+
+typedef struct dn_conv_desc {
+    int batch, in_h, in_w, in_c;   /* logical input (NHWC storage, channels padded) */
+    int cout, ksize, stride, pad;
+    int activation;
+    float leaky_slope;
+    int pool;        /* 0, or 2 = fused 2x2 stride-2 max pool (output side / 2) */
+    int residual;    /* 1 = add `res` (output-shaped NHWC tensor) after the activation */
+    int dtype;
+    float in_scale;  /* FP8: x = q * in_scale (else ignored) */
+    float res_scale; /* FP8: res = q * res_scale */
+    float out_scale; /* FP8: y_q = y / out_scale */
+    int tile;        /* -1 = library heuristic, else a tile config index */
+    int splits;      /* 0 = library heuristic, else split-K factor */
+} dn_conv_desc;
+
+/* Bytes of the packed weight buffer, the FP32 bias / weight-scale buffers
+ * and the split-K scratch the conv needs. */
+dn_status dn_conv_sizes(const dn_conv_desc *d, size_t *w_bytes, size_t *vec_bytes, size_t *ws_bytes);
+
+/* FP64 BN fold + round + pack of host parameters (same meaning as
+ * dn_load_weights) into caller device buffers w_packed, bias (FP32),
+ * wscale (FP32; all ones unless FP8).  Synchronous on `stream`. */
+dn_status dn_conv_pack(const dn_conv_desc *d, const double *w, const double *bias,
+                       const double *mean, const double *var, const double *gamma,
+                       const double *beta, double eps, void *w_packed, float *bias_out,
+                       float *wscale_out, void *stream);
+
+/* Implicit-GEMM convolution (M = batch*Ho*Wo, N = cout, K = k*k*Cin_pad)
+ * with the fused epilogue: +bias', activation, [+res], [2x2 max], round.
+ * x, y, res, workspace: device.  Enqueue only. */
+dn_status dn_conv2d(const dn_conv_desc *d, const void *x, const void *w_packed,
+                    const float *bias, const float *wscale, const void *res, void *y,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+typedef struct dn_pool_desc {
+    int batch, h, w, c, size, stride, dtype;
+} dn_pool_desc;
+
+/* Max pool over NHWC device tensors (FP8: input and output share one scale). */
+dn_status dn_maxpool(const dn_pool_desc *d, const void *x, void *y, void *stream);
+
+/* y = a + b over NHWC device tensors of `count` padded elements
+ * (FP8: values scaled by sa, sb, result divided by sy). */
+dn_status dn_shortcut(int dtype, size_t count, const void *a, float sa, const void *b, float sb,
+                      void *y, float sy, void *stream);
+
+/* NCHW FP32 (device) -> NHWC storage dtype with padded channels. */
+dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, float scale,
+                    void *y, void *stream);
+
+/* NHWC storage dtype (padded channels) -> NCHW FP32 (device). */
+dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
+                    float *y, void *stream);
+
+/* Number of compiled conv tile configurations and their shapes. */
+int dn_tile_count(void);
+dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n);
+
+const char *dn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DN_H */

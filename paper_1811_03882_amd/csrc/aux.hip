@@ -1,0 +1,344 @@
+// Memory-bound kernels around the convolutions: FP64 batch-norm fold and
+// weight packing (load time), input ingest and output egress (once per
+// forward), standalone max pool and residual add (per-layer mode and the
+// layers that cannot be fused), and the amax reduction used for FP8
+// calibration.  All activations are NHWC with 16-byte padded channels; every
+// kernel moves whole 16-byte segments where the layout allows it.
+#include "dn_kernels.h"
+
+namespace dnk {
+
+// ---------------------------------------------------------------- conversions
+// (same rounding as the conv epilogue: nearest even; FP8 saturates at +-448)
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ uint32_t f2e4m3(float f)
+{
+    f = fminf(fmaxf(f, -448.0f), 448.0f);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(f, f, 0, false) & 0xFFu;
+}
+__device__ __forceinline__ float e4m32f(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+
+// Decode / encode one 16-byte segment (4, 8 or 16 elements) to/from floats.
+template <int DT> struct Seg;
+template <> struct Seg<F32> {
+    static constexpr int N = 4;
+    __device__ static void dec(uint4 u, float *f) { f[0] = __uint_as_float(u.x); f[1] = __uint_as_float(u.y); f[2] = __uint_as_float(u.z); f[3] = __uint_as_float(u.w); }
+    __device__ static uint4 enc(const float *f) { return make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3])); }
+};
+template <> struct Seg<BF16> {
+    static constexpr int N = 8;
+    __device__ static void dec(uint4 u, float *f)
+    {
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        for (int i = 0; i < 4; ++i) { f[2 * i] = bf2f(w[i] & 0xFFFFu); f[2 * i + 1] = bf2f(w[i] >> 16); }
+    }
+    __device__ static uint4 enc(const float *f)
+    {
+        uint32_t w[4];
+        for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+};
+template <> struct Seg<FP8> {
+    static constexpr int N = 16;
+    __device__ static void dec(uint4 u, float *f)
+    {
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) f[4 * i + j] = e4m32f((w[i] >> (8 * j)) & 0xFFu);
+    }
+    __device__ static uint4 enc(const float *f)
+    {
+        uint32_t w[4];
+        for (int i = 0; i < 4; ++i)
+            w[i] = f2e4m3(f[4 * i]) | (f2e4m3(f[4 * i + 1]) << 8) | (f2e4m3(f[4 * i + 2]) << 16) | (f2e4m3(f[4 * i + 3]) << 24);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+};
+
+// ---------------------------------------------------------------- fold + pack
+// One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
+// w' = w * scale, b' = (b - mean) * scale + beta (b' = b without BN).  The
+// packed row is [k_pad] with k = (r*S + s)*cin_p + c, zeros in every padding.
+// FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
+
+template <int DT>
+__global__ void __launch_bounds__(256) fold_pack(const double *w, const double *bias, const double *mean,
+                                                 const double *var, const double *gamma, const double *beta,
+                                                 double eps, int has_bn, int cout, int cin, int R, int S,
+                                                 int cin_p, int k_pad, void *wout, float *bout, float *sout)
+{
+    const int co = blockIdx.x;
+    const int RS = R * S;
+    double sc = 1.0, bb = 0.0;
+    if (co < cout) {
+        if (has_bn) {
+            sc = gamma[co] / sqrt(var[co] + eps);
+            bb = (bias[co] - mean[co]) * sc + beta[co];
+        } else {
+            bb = bias[co];
+        }
+    }
+    auto wval = [&](int k) -> double {
+        const int tap = k / cin_p, c = k - tap * cin_p;
+        if (co >= cout || tap >= RS || c >= cin) return 0.0;
+        const int r = tap / S, s = tap - r * S;
+        return w[(((size_t)co * cin + c) * R + r) * S + s] * sc;
+    };
+    double qs = 1.0;
+    if (DT == FP8) {
+        __shared__ double red[256];
+        double mx = 0.0;
+        for (int k = threadIdx.x; k < k_pad; k += blockDim.x) mx = fmax(mx, fabs(wval(k)));
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+            __syncthreads();
+        }
+        qs = red[0] > 0.0 ? red[0] / 448.0 : 1.0;
+    }
+    for (int k = threadIdx.x; k < k_pad; k += blockDim.x) {
+        const double v = wval(k);
+        const size_t o = (size_t)co * k_pad + k;
+        if (DT == F32) ((float *)wout)[o] = (float)v;
+        else if (DT == BF16) ((uint16_t *)wout)[o] = f2bf((float)v);
+        else ((uint8_t *)wout)[o] = (uint8_t)f2e4m3((float)(v / qs));
+    }
+    if (threadIdx.x == 0) {
+        bout[co] = (float)bb;
+        sout[co] = (float)qs;
+    }
+}
+
+hipError_t launch_fold_pack(int dt, const double *w, const double *bias, const double *mean,
+                            const double *var, const double *gamma, const double *beta, double eps,
+                            int has_bn, int cout, int cin, int R, int S, int cin_p, int k_pad,
+                            int cout_p, void *wout, float *bout, float *sout, hipStream_t s)
+{
+    dim3 g(cout_p), b(256);
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(fold_pack<F32>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case BF16: hipLaunchKernelGGL(fold_pack<BF16>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case FP8: hipLaunchKernelGGL(fold_pack<FP8>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- ingest
+// NCHW FP32 -> NHWC storage type.  One thread per (pixel, 16-byte segment):
+// consecutive threads read consecutive pixels of one channel plane.
+
+template <int DT>
+__global__ void __launch_bounds__(256) ingest(const float *x, int n, int c, int hw, int cp, float inv_scale, void *y)
+{
+    constexpr int E = Seg<DT>::N;
+    const int nseg = cp / E;
+    const size_t total = (size_t)n * hw * nseg;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int p = (int)(t % hw);
+    const size_t rest = t / hw;
+    const int sg = (int)(rest % nseg);
+    const int img = (int)(rest / nseg);
+    float f[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int ch = sg * E + e;
+        f[e] = ch < c ? x[((size_t)img * c + ch) * hw + p] * inv_scale : 0.0f;
+    }
+    ((uint4 *)y)[((size_t)img * hw + p) * nseg + sg] = Seg<DT>::enc(f);
+}
+
+hipError_t launch_ingest(int dt, const float *x, int n, int c, int h, int w, int cp, float inv_scale,
+                         void *y, hipStream_t s)
+{
+    const size_t total = (size_t)n * h * w * (cp / seg_el(dt));
+    if (total == 0) return hipSuccess;
+    dim3 g((unsigned)((total + 255) / 256)), b(256);
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(ingest<F32>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
+    case BF16: hipLaunchKernelGGL(ingest<BF16>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
+    case FP8: hipLaunchKernelGGL(ingest<FP8>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- egress
+// NHWC storage type -> NCHW FP32; thread per (pixel, segment), consecutive
+// threads write consecutive pixels of a channel plane.
+
+template <int DT>
+__global__ void __launch_bounds__(256) egress(const void *x, int n, int c, int hw, int cp, float scale, float *y)
+{
+    constexpr int E = Seg<DT>::N;
+    const int nseg = (c + E - 1) / E, cseg = cp / E;
+    const size_t total = (size_t)n * hw * nseg;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int p = (int)(t % hw);
+    const size_t rest = t / hw;
+    const int sg = (int)(rest % nseg);
+    const int img = (int)(rest / nseg);
+    float f[E];
+    Seg<DT>::dec(((const uint4 *)x)[((size_t)img * hw + p) * cseg + sg], f);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int ch = sg * E + e;
+        if (ch < c) y[((size_t)img * c + ch) * hw + p] = f[e] * scale;
+    }
+}
+
+hipError_t launch_egress(int dt, const void *x, int n, int c, int h, int w, int cp, float scale,
+                         float *y, hipStream_t s)
+{
+    const size_t total = (size_t)n * h * w * ((c + seg_el(dt) - 1) / seg_el(dt));
+    if (total == 0) return hipSuccess;
+    dim3 g((unsigned)((total + 255) / 256)), b(256);
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(egress<F32>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
+    case BF16: hipLaunchKernelGGL(egress<BF16>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
+    case FP8: hipLaunchKernelGGL(egress<FP8>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- max pool
+// -inf outside the input; window starts at i*stride - (size-1)/2.  Values are
+// decoded, compared and re-encoded, which is exact (no new values appear).
+
+template <int DT>
+__global__ void __launch_bounds__(256) maxpool(const void *x, void *y, int n, int h, int w, int cp, int size,
+                                               int stride, int ho, int wo)
+{
+    constexpr int E = Seg<DT>::N;
+    const int nseg = cp / E;
+    const size_t total = (size_t)n * ho * wo * nseg;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int sg = (int)(t % nseg);
+    const size_t p = t / nseg;
+    const int j = (int)(p % wo);
+    const size_t q = p / wo;
+    const int i = (int)(q % ho);
+    const int img = (int)(q / ho);
+    const int off = (size - 1) / 2;
+    float m[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) m[e] = -INFINITY;
+    for (int u = 0; u < size; ++u) {
+        const int yy = i * stride - off + u;
+        if (yy < 0 || yy >= h) continue;
+        for (int v = 0; v < size; ++v) {
+            const int xx = j * stride - off + v;
+            if (xx < 0 || xx >= w) continue;
+            float f[E];
+            Seg<DT>::dec(((const uint4 *)x)[(((size_t)img * h + yy) * w + xx) * nseg + sg], f);
+#pragma unroll
+            for (int e = 0; e < E; ++e) m[e] = fmaxf(m[e], f[e]);
+        }
+    }
+    ((uint4 *)y)[p * nseg + sg] = Seg<DT>::enc(m);
+}
+
+hipError_t launch_maxpool(int dt, const void *x, void *y, int n, int h, int w, int cp, int size,
+                          int stride, int ho, int wo, hipStream_t s)
+{
+    const size_t total = (size_t)n * ho * wo * (cp / seg_el(dt));
+    if (total == 0) return hipSuccess;
+    dim3 g((unsigned)((total + 255) / 256)), b(256);
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(maxpool<F32>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
+    case BF16: hipLaunchKernelGGL(maxpool<BF16>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
+    case FP8: hipLaunchKernelGGL(maxpool<FP8>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- residual add
+
+template <int DT>
+__global__ void __launch_bounds__(256) add_seg(const uint4 *a, float sa, const uint4 *b, float sb, uint4 *y,
+                                               float inv_sy, size_t nseg)
+{
+    constexpr int E = Seg<DT>::N;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nseg) return;
+    float fa[E], fb[E];
+    Seg<DT>::dec(a[t], fa);
+    Seg<DT>::dec(b[t], fb);
+#pragma unroll
+    for (int e = 0; e < E; ++e) fa[e] = (fa[e] * sa + fb[e] * sb) * inv_sy;
+    y[t] = Seg<DT>::enc(fa);
+}
+
+hipError_t launch_add(int dt, const void *a, float sa, const void *b, float sb, void *y, float inv_sy,
+                      size_t count, hipStream_t s)
+{
+    const size_t nseg = count / seg_el(dt);
+    if (nseg == 0) return hipSuccess;
+    dim3 g((unsigned)((nseg + 255) / 256)), bl(256);
+    const uint4 *A = (const uint4 *)a, *B = (const uint4 *)b;
+    uint4 *Y = (uint4 *)y;
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(add_seg<F32>, g, bl, 0, s, A, sa, B, sb, Y, inv_sy, nseg); break;
+    case BF16: hipLaunchKernelGGL(add_seg<BF16>, g, bl, 0, s, A, sa, B, sb, Y, inv_sy, nseg); break;
+    case FP8: hipLaunchKernelGGL(add_seg<FP8>, g, bl, 0, s, A, sa, B, sb, Y, inv_sy, nseg); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- amax
+// |x| >= 0, so the IEEE bit pattern orders like an unsigned integer and the
+// block maxima combine with a 32-bit atomic max.
+
+__global__ void __launch_bounds__(256) amax_kernel(const float *x, size_t n, unsigned *out)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+hipError_t launch_amax(const float *x, size_t count, float *out, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(amax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, count, (unsigned *)out);
+    return hipGetLastError();
+}
+
+__global__ void zero_kernel(float *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace dnk

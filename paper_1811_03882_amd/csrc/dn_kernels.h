@@ -1,0 +1,73 @@
+// Internal interface between the runtime (runtime.cpp) and the HIP kernels
+// (conv.hip, aux.hip) of the Darknet-style CNN forward library.  Not part of
+// the public C ABI (include/dn.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dnk {
+
+enum { F32 = 0, BF16 = 1, FP8 = 2 };
+
+__host__ __device__ constexpr int esize(int dt) { return dt == F32 ? 4 : dt == BF16 ? 2 : 1; }
+// Elements per 16-byte segment: the unit of every global load and of the
+// channel padding of NHWC activations.
+__host__ __device__ constexpr int seg_el(int dt) { return 16 / esize(dt); }
+__host__ __device__ constexpr int cpad(int dt, int c) { return (c + seg_el(dt) - 1) / seg_el(dt) * seg_el(dt); }
+// K-tile of the implicit GEMM: 128 bytes of one A/B row (8 segments).
+__host__ __device__ constexpr int bk_el(int dt) { return 128 / esize(dt); }
+
+// Arguments of one implicit-GEMM convolution launch.
+//   A[m][k] = x[n][ho*st - pad + r][wo*st - pad + s][c],  k = (r*S + s)*cin_p + c
+//   B[k][j] = w_packed[j][k]   (packed [cout_p][k_pad], K contiguous)
+//   m runs over (n, ho, wo), or over (n, ho/2, wo/2, dy, dx) when pool = 1 so
+//   that each 2x2 pooling window is four consecutive rows.
+struct ConvArgs {
+    const void *x;
+    const void *w;
+    const float *bias;     // [cout_p] folded bias
+    const float *wscale;   // [cout_p] FP8 per-channel weight scale (else unused)
+    const void *res;       // residual, output-shaped NHWC, or nullptr
+    void *y;               // NHWC output with cout_p channels
+    float *partial;        // split-K scratch [splits][M][cout_p] FP32
+    int batch, H, W, cin_p;
+    int Ho, Wo, cout_p;
+    int R, S, stride, pad;
+    int k_pad;             // multiple of bk_el(dtype); K = R*S*cin_p <= k_pad
+    int M;                 // batch*Ho*Wo
+    int pool;              // fused 2x2 stride-2 max pool
+    int act;               // 0 linear, 1 leaky
+    float slope;
+    float in_scale, res_scale, out_inv_scale;  // FP8 scales (1 otherwise)
+    int splits, ktiles_per_split;
+};
+
+struct TileCfg { int bm, bn, wm, wn; };
+
+int tile_count();
+TileCfg tile_cfg(int i);
+// Launch the conv (one GEMM launch; for splits > 1 it writes partials and
+// launch_splitk_reduce finishes the epilogue).
+hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
+hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
+
+hipError_t launch_fold_pack(int dt, const double *w, const double *bias, const double *mean,
+                            const double *var, const double *gamma, const double *beta,
+                            double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,
+                            int k_pad, int cout_p, void *wout, float *bout, float *sout,
+                            hipStream_t s);
+hipError_t launch_ingest(int dt, const float *x, int n, int c, int h, int w, int cp,
+                         float inv_scale, void *y, hipStream_t s);
+hipError_t launch_egress(int dt, const void *x, int n, int c, int h, int w, int cp, float scale,
+                         float *y, hipStream_t s);
+hipError_t launch_maxpool(int dt, const void *x, void *y, int n, int h, int w, int cp, int size,
+                          int stride, int ho, int wo, hipStream_t s);
+hipError_t launch_add(int dt, const void *a, float sa, const void *b, float sb, void *y,
+                      float inv_sy, size_t count, hipStream_t s);
+// amax of |x| over `count` FP32 values, max-combined into *out (caller zeroes *out).
+hipError_t launch_amax(const float *x, size_t count, float *out, hipStream_t s);
+hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s);
+
+}  // namespace dnk

@@ -1,0 +1,1135 @@
+// Host runtime and C ABI (include/dn.h) of the Darknet-style CNN forward
+// library: layer-list validation, the execution plan with its fusions, the
+// liveness-packed activation arena, weight upload / FP64 fold, the resident
+// and per-layer-transfer forwards, hipGraph capture/replay, FP8 calibration
+// and the tile autotuner.
+//
+// Transfer placement follows the rule of Sec. 3.2 of the paper: a copy is
+// placed outside the outermost loop that does not define (host->device) or
+// use (device->host) the data.  Weights are defined once per load, so they
+// cross once in dn_load_weights; the input is defined once per frame, so it
+// crosses once per forward; intermediate activations are produced and
+// consumed on the device only, so they never cross.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dn.h"
+#include "dn_kernels.h"
+
+using namespace dnk;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+static dn_status fail(dn_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static dn_status fail(dn_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(DN_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define STCHK(expr)                     \
+    do {                                \
+        dn_status s_ = (expr);          \
+        if (s_ != DN_OK) return s_;     \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- net objects
+
+struct ConvWeights {
+    int cin = 0, cin_p = 0, cout = 0, cout_p = 0, k_pad = 0;
+    int k_pad32 = 0;          // k_pad of the FP32 calibration copy
+    void *w = nullptr;        // packed, net dtype
+    float *bias = nullptr;    // [cout_p]
+    float *wscale = nullptr;  // [cout_p]
+    void *w32 = nullptr;      // FP8 nets: FP32 packed copy for calibration
+    float *bias32 = nullptr, *wscale32 = nullptr;
+    std::vector<unsigned char> host_w;  // per-layer mode: host copy of the packed weights
+    std::vector<float> host_bias, host_wscale;
+    void *pinned = nullptr;   // pinned staging of host_w|bias|wscale (per-layer mode)
+    size_t wbytes = 0;
+    bool loaded = false;
+};
+
+enum OpKind { OP_CONV = 0, OP_POOL = 1, OP_ADD = 2 };
+
+struct Op {
+    int kind = OP_CONV;
+    int layer = 0;       // layer index whose output this op produces
+    int conv = -1;       // conv layer index (OP_CONV)
+    int in = 0, in2 = -1, out = 0;  // value ids: value v = output of layer v-1, value 0 = net input
+    bool pool = false, res = false;
+    int H = 0, W = 0, Ho = 0, Wo = 0, cin_p = 0, cout = 0, cout_p = 0;  // op geometry
+    int c_log = 0;       // logical channels of the output
+    int tile = -1, splits = 1;
+    size_t ws_bytes = 0;
+};
+
+struct Value { int c = 0, cp = 0, h = 0, w = 0; size_t bytes = 0, off = 0; int first = 0, last = 0; };
+
+struct Plan {
+    int dtype = 0, mode = 0, batch = 0, h = 0, w = 0;
+    std::vector<Op> ops;
+    std::vector<Value> vals;   // index = value id
+    size_t ws_off = 0, ws_bytes = 0;
+    size_t xin_off = 0, yout_off = 0;  // per-layer mode FP32 staging of x / y
+    size_t total = 0;
+    int out_val = 0;
+};
+
+struct GraphKey {
+    int batch, h, w;
+    const void *x, *y, *arena;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(batch, h, w, x, y, arena) < std::tie(o.batch, o.h, o.w, o.x, o.y, o.arena);
+    }
+};
+
+struct dn_net {
+    std::vector<dn_layer_desc> L;
+    dn_net_opts o{};
+    std::vector<ConvWeights> cw;            // per layer (only convs used)
+    std::vector<int> in_c;                  // logical input channels per layer
+    std::vector<float> scale;               // FP8: per value (index = value id) activation scale
+    bool calibrated = false;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t cap_stream = nullptr;       // capture stream (never the legacy null stream)
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
+    std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
+    std::mutex mu;
+};
+
+// ---------------------------------------------------------------- helpers
+
+static int out_side_conv(int x, int k, int st, int pad) { return (x + 2 * pad - k) / st + 1; }
+static int out_side_pool(int x, int st) { return (x - 1) / st + 1; }
+
+extern "C" int dn_channel_pad(int dtype, int c)
+{
+    if (dtype < 0 || dtype > 2 || c < 0) return -1;
+    return cpad(dtype, c);
+}
+
+static dn_status check_dtype(int dt)
+{
+    if (dt != DN_F32 && dt != DN_BF16 && dt != DN_FP8_E4M3) return fail(DN_EINVAL, "unknown dtype %d", dt);
+    return DN_OK;
+}
+
+// Heuristic tile when the autotuner has not run: largest tile that still
+// gives >= 1 workgroup per CU, small-N tiles for narrow layers.
+static void heuristic_tile(int M, int N, int K, int *tile, int *splits)
+{
+    const int CUS = 256;
+    int best = 2;
+    if (N <= 16) best = 6;
+    else if (N <= 32) best = 7;
+    else if (N <= 64) best = (M >= 256 * 64) ? 1 : 0;
+    else {
+        const int cands[] = {4, 3, 2, 8, 0};
+        best = 0;
+        for (int c : cands) {
+            const TileCfg t = tile_cfg(c);
+            const long tiles = (long)((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
+            if (tiles >= CUS) { best = c; break; }
+        }
+    }
+    const TileCfg t = tile_cfg(best);
+    const long tiles = (long)((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
+    int s = 1;
+    const int ktiles = K;  // caller passes K in k-tiles
+    while (tiles * s * 2 <= 2 * CUS && ktiles / (s * 2) >= 4) s *= 2;
+    *tile = best;
+    *splits = s;
+}
+
+static std::string conv_sig(int dt, const Op &op, int batch, int R, int stride)
+{
+    char b[256];
+    snprintf(b, sizeof b, "dt%d_b%d_H%d_W%d_ci%d_co%d_R%d_s%d_p%d_r%d", dt, batch, op.H, op.W, op.cin_p,
+             op.cout_p, R, stride, (int)op.pool, (int)op.res);
+    return b;
+}
+
+// Fill ConvArgs for an op of plan p, reading from base (arena).
+static ConvArgs conv_args(const dn_net *net, const Plan &p, const Op &op, char *base, bool use32)
+{
+    const dn_layer_desc &d = net->L[op.conv];
+    const ConvWeights &cw = net->cw[op.conv];
+    ConvArgs a{};
+    a.x = base + p.vals[op.in].off;
+    a.w = use32 ? cw.w32 : cw.w;
+    a.bias = use32 ? cw.bias32 : cw.bias;
+    a.wscale = use32 ? cw.wscale32 : cw.wscale;
+    a.res = op.res ? base + p.vals[op.in2].off : nullptr;
+    a.y = base + p.vals[op.out].off;
+    a.partial = (float *)(base + p.ws_off);
+    a.batch = p.batch;
+    a.H = op.H; a.W = op.W; a.cin_p = op.cin_p;
+    a.Ho = op.pool ? op.Ho * 2 : op.Ho;
+    a.Wo = op.pool ? op.Wo * 2 : op.Wo;
+    a.cout_p = op.cout_p;
+    a.R = d.ksize; a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
+    a.k_pad = use32 ? cw.k_pad32 : cw.k_pad;
+    a.M = p.batch * a.Ho * a.Wo;
+    a.pool = op.pool ? 1 : 0;
+    a.act = d.activation;
+    a.slope = net->o.leaky_slope;
+    a.in_scale = a.res_scale = a.out_inv_scale = 1.0f;
+    if (p.dtype == FP8) {
+        a.in_scale = net->scale[op.in];
+        a.res_scale = op.res ? net->scale[op.in2] : 1.0f;
+        a.out_inv_scale = 1.0f / net->scale[op.out];
+    }
+    a.splits = op.splits;
+    const int nkt = a.k_pad / bk_el(use32 ? (int)F32 : p.dtype);
+    a.ktiles_per_split = (nkt + op.splits - 1) / op.splits;
+    return a;
+}
+
+// ---------------------------------------------------------------- planning
+
+static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, int h, int w, Plan *out)
+{
+    const int n = (int)net->L.size();
+    if (batch <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "batch/h/w must be positive (%d, %d, %d)", batch, h, w);
+    Plan p;
+    p.dtype = dtype; p.mode = mode; p.batch = batch; p.h = h; p.w = w;
+    const int es = esize(dtype);
+    // value geometry
+    p.vals.resize(n + 1);
+    p.vals[0].c = net->o.in_c; p.vals[0].h = h; p.vals[0].w = w;
+    for (int i = 0; i < n; ++i) {
+        const dn_layer_desc &d = net->L[i];
+        const Value &in = p.vals[i];
+        Value &v = p.vals[i + 1];
+        if (d.kind == DN_CONV) {
+            v.c = d.cout;
+            v.h = out_side_conv(in.h, d.ksize, d.stride, d.pad);
+            v.w = out_side_conv(in.w, d.ksize, d.stride, d.pad);
+        } else if (d.kind == DN_MAXPOOL) {
+            v.c = in.c; v.h = out_side_pool(in.h, d.stride); v.w = out_side_pool(in.w, d.stride);
+        } else {
+            const Value &s = p.vals[d.src + 1];
+            if (s.c != in.c || s.h != in.h || s.w != in.w)
+                return fail(DN_EINVAL, "shortcut layer %d: shape of layer %d (%dx%dx%d) != previous (%dx%dx%d)", i, d.src, s.c, s.h, s.w, in.c, in.h, in.w);
+            v = in;
+        }
+        if (v.h <= 0 || v.w <= 0) return fail(DN_EINVAL, "input %dx%d too small for layer %d", h, w, i);
+    }
+    for (auto &v : p.vals) {
+        v.cp = cpad(dtype, v.c);
+        v.bytes = align256((size_t)batch * v.h * v.w * v.cp * es);
+        v.first = -2; v.last = -2;
+    }
+    // consumers count (to know whether a conv output may be fused away)
+    std::vector<int> uses(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        uses[i]++;  // layer i reads value i (its input)
+        if (net->L[i].kind == DN_SHORTCUT) uses[net->L[i].src + 1]++;
+    }
+    uses[n]++;  // net output
+    // ops
+    for (int i = 0; i < n; ++i) {
+        const dn_layer_desc &d = net->L[i];
+        Op op;
+        op.layer = i;
+        op.in = i;
+        op.out = i + 1;
+        op.c_log = p.vals[i + 1].c;
+        if (d.kind == DN_CONV) {
+            op.kind = OP_CONV;
+            op.conv = i;
+            op.H = p.vals[i].h; op.W = p.vals[i].w; op.cin_p = p.vals[i].cp;
+            op.Ho = p.vals[i + 1].h; op.Wo = p.vals[i + 1].w;
+            op.cout = d.cout; op.cout_p = p.vals[i + 1].cp;
+            if (mode == DN_MODE_RESIDENT && i + 1 < n && uses[i + 1] == 1) {
+                const dn_layer_desc &nx = net->L[i + 1];
+                if (nx.kind == DN_MAXPOOL && nx.ksize == 2 && nx.stride == 2 && op.Ho % 2 == 0 && op.Wo % 2 == 0) {
+                    op.pool = true;
+                    op.layer = i + 1; op.out = i + 2;
+                    op.Ho /= 2; op.Wo /= 2;
+                    ++i;
+                } else if (nx.kind == DN_SHORTCUT && nx.src != i && nx.activation == DN_ACT_LINEAR) {
+                    op.res = true;
+                    op.in2 = nx.src + 1;
+                    op.layer = i + 1; op.out = i + 2;
+                    ++i;
+                }
+            }
+        } else if (d.kind == DN_MAXPOOL) {
+            op.kind = OP_POOL;
+            op.H = p.vals[i].h; op.W = p.vals[i].w; op.Ho = p.vals[i + 1].h; op.Wo = p.vals[i + 1].w;
+            op.cout_p = p.vals[i + 1].cp;
+        } else {
+            op.kind = OP_ADD;
+            op.in2 = d.src + 1;
+            op.cout_p = p.vals[i + 1].cp;
+        }
+        p.ops.push_back(op);
+    }
+    // liveness: value produced at op index (value 0 at -1), last use = max consumer op index
+    p.vals[0].first = -1;
+    for (int k = 0; k < (int)p.ops.size(); ++k) {
+        Op &op = p.ops[k];
+        p.vals[op.out].first = k;
+        p.vals[op.in].last = std::max(p.vals[op.in].last, k);
+        if (op.in2 >= 0) p.vals[op.in2].last = std::max(p.vals[op.in2].last, k);
+    }
+    p.out_val = p.ops.back().out;
+    p.vals[p.out_val].last = (int)p.ops.size();  // egress
+    // greedy first-fit placement in production order
+    std::vector<std::pair<size_t, size_t>> live;  // (off, size) of live blocks with their value id below
+    std::vector<int> live_id;
+    size_t top = 0;
+    auto place = [&](int vid) {
+        std::vector<std::pair<size_t, size_t>> blocks = live;
+        std::sort(blocks.begin(), blocks.end());
+        size_t cur = 0;
+        for (auto &b : blocks) {
+            if (b.first >= cur + p.vals[vid].bytes) break;
+            cur = std::max(cur, b.first + b.second);
+        }
+        p.vals[vid].off = cur;
+        top = std::max(top, cur + p.vals[vid].bytes);
+        live.push_back({cur, p.vals[vid].bytes});
+        live_id.push_back(vid);
+    };
+    auto release = [&](int k) {
+        for (size_t j = 0; j < live.size();) {
+            if (p.vals[live_id[j]].last == k) {
+                live.erase(live.begin() + j);
+                live_id.erase(live_id.begin() + j);
+            } else {
+                ++j;
+            }
+        }
+    };
+    place(0);
+    for (int k = 0; k < (int)p.ops.size(); ++k) {
+        place(p.ops[k].out);
+        release(k);
+    }
+    // split-K scratch and tile choice
+    size_t ws = 0;
+    for (Op &op : p.ops) {
+        if (op.kind != OP_CONV) continue;
+        const dn_layer_desc &d = net->L[op.conv];
+        const int K = d.ksize * d.ksize * op.cin_p;
+        const int k_pad = (K + bk_el(dtype) - 1) / bk_el(dtype) * bk_el(dtype);
+        const int M = op.pool ? batch * (2 * op.Ho) * (2 * op.Wo) : batch * op.Ho * op.Wo;
+        const std::string sig = conv_sig(dtype, op, batch, d.ksize, d.stride);
+        auto it = net->tuned.find(sig);
+        if (it != net->tuned.end()) {
+            op.tile = it->second.first;
+            op.splits = it->second.second;
+        } else {
+            heuristic_tile(M, op.cout_p, k_pad / bk_el(dtype), &op.tile, &op.splits);
+        }
+        op.ws_bytes = op.splits > 1 ? align256((size_t)op.splits * M * op.cout_p * 4) : 0;
+        ws = std::max(ws, op.ws_bytes);
+    }
+    p.ws_off = align256(top);
+    p.ws_bytes = ws;
+    size_t end = p.ws_off + ws;
+    if (mode == DN_MODE_PER_LAYER) {
+        p.xin_off = align256(end);
+        end = p.xin_off + align256((size_t)batch * net->o.in_c * h * w * 4);
+        p.yout_off = align256(end);
+        const Value &ov = p.vals[p.out_val];
+        end = p.yout_off + align256((size_t)batch * ov.c * ov.h * ov.w * 4);
+    }
+    p.total = align256(end);
+    *out = std::move(p);
+    return DN_OK;
+}
+
+// ---------------------------------------------------------------- enqueue
+
+static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char *base, hipStream_t s, bool use32,
+                            int tile_override = -1, int splits_override = 0)
+{
+    if (op.kind == OP_CONV) {
+        Op o2 = op;
+        if (tile_override >= 0) o2.tile = tile_override;
+        if (splits_override > 0) o2.splits = splits_override;
+        ConvArgs a = conv_args(net, p, o2, base, use32);
+        const int dt = use32 ? F32 : p.dtype;
+        HIPCHK(launch_conv(dt, o2.tile, a, s));
+        if (o2.splits > 1) HIPCHK(launch_splitk_reduce(dt, a, s));
+    } else if (op.kind == OP_POOL) {
+        const dn_layer_desc &d = net->L[op.layer];
+        const Value &vi = p.vals[op.in];
+        HIPCHK(launch_maxpool(use32 ? F32 : p.dtype, base + vi.off, base + p.vals[op.out].off, p.batch, vi.h, vi.w,
+                              vi.cp, d.ksize, d.stride, op.Ho, op.Wo, s));
+    } else {
+        const Value &vo = p.vals[op.out];
+        float sa = 1.f, sb = 1.f, isy = 1.f;
+        if (!use32 && p.dtype == FP8) {
+            sa = net->scale[op.in]; sb = net->scale[op.in2]; isy = 1.0f / net->scale[op.out];
+        }
+        HIPCHK(launch_add(use32 ? F32 : p.dtype, base + p.vals[op.in].off, sa, base + p.vals[op.in2].off, sb,
+                          base + vo.off, isy, (size_t)p.batch * vo.h * vo.w * vo.cp, s));
+    }
+    return DN_OK;
+}
+
+static dn_status enqueue_resident(const dn_net *net, const Plan &p, char *base, const float *x, float *y, hipStream_t s)
+{
+    const Value &v0 = p.vals[0];
+    const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
+    HIPCHK(launch_ingest(p.dtype, x, p.batch, v0.c, v0.h, v0.w, v0.cp, in_inv, base + v0.off, s));
+    for (const Op &op : p.ops) STCHK(enqueue_op(net, p, op, base, s, false));
+    const Value &vo = p.vals[p.out_val];
+    const float osc = p.dtype == FP8 ? net->scale[p.out_val] : 1.0f;
+    HIPCHK(launch_egress(p.dtype, base + vo.off, p.batch, vo.c, vo.h, vo.w, vo.cp, osc, y, s));
+    return DN_OK;
+}
+
+static dn_status check_ready(const dn_net *net, bool need_calib)
+{
+    for (size_t i = 0; i < net->L.size(); ++i)
+        if (net->L[i].kind == DN_CONV && !net->cw[i].loaded)
+            return fail(DN_ESTATE, "weights of conv layer %zu not loaded", i);
+    if (need_calib && net->o.dtype == DN_FP8_E4M3 && !net->calibrated)
+        return fail(DN_ESTATE, "FP8 net used before dn_calibrate");
+    return DN_OK;
+}
+
+static dn_status check_dims(const dn_net *net, int batch, int h, int w)
+{
+    if (batch <= 0 || batch > net->o.max_batch) return fail(DN_EINVAL, "batch %d outside 1..%d", batch, net->o.max_batch);
+    if (h <= 0 || w <= 0 || h > net->o.max_h || w > net->o.max_w)
+        return fail(DN_EINVAL, "input %dx%d outside 1..%dx%d", h, w, net->o.max_h, net->o.max_w);
+    return DN_OK;
+}
+
+static bool is_device_ptr(const void *p)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" const char *dn_last_error(void) { return g_err.c_str(); }
+
+extern "C" dn_status dn_net_create(const dn_layer_desc *layers, int n, const dn_net_opts *o, dn_net **out)
+{
+    if (!out) return fail(DN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!layers || n <= 0 || !o) return fail(DN_EINVAL, "need a non-empty layer list and options");
+    STCHK(check_dtype(o->dtype));
+    if (o->mode != DN_MODE_RESIDENT && o->mode != DN_MODE_PER_LAYER) return fail(DN_EINVAL, "unknown mode %d", o->mode);
+    if (o->in_c <= 0 || o->in_c > 16) return fail(DN_EINVAL, "in_c %d outside 1..16", o->in_c);
+    if (o->max_h <= 0 || o->max_w <= 0 || o->max_batch <= 0) return fail(DN_EINVAL, "max_h/max_w/max_batch must be positive");
+    if (!(o->bn_eps > 0.0)) return fail(DN_EINVAL, "bn_eps must be > 0");
+    int c = o->in_c;
+    std::vector<int> chans;
+    for (int i = 0; i < n; ++i) {
+        const dn_layer_desc &d = layers[i];
+        chans.push_back(c);
+        if (d.kind == DN_CONV) {
+            if (d.cout <= 0 || d.ksize <= 0 || d.stride <= 0 || d.pad < 0)
+                return fail(DN_EINVAL, "conv layer %d: bad cout/ksize/stride/pad", i);
+            if (d.activation != DN_ACT_LINEAR && d.activation != DN_ACT_LEAKY)
+                return fail(DN_EINVAL, "conv layer %d: unknown activation %d", i, d.activation);
+            c = d.cout;
+        } else if (d.kind == DN_MAXPOOL) {
+            if (d.ksize <= 0 || d.stride <= 0) return fail(DN_EINVAL, "maxpool layer %d: bad size/stride", i);
+        } else if (d.kind == DN_SHORTCUT) {
+            if (d.src < 0 || d.src >= i)
+                return fail(DN_EINVAL, "shortcut layer %d: src %d must name an earlier layer", i, d.src);
+            if (d.activation != DN_ACT_LINEAR && d.activation != DN_ACT_LEAKY)
+                return fail(DN_EINVAL, "shortcut layer %d: unknown activation", i);
+        } else {
+            return fail(DN_EINVAL, "layer %d: unknown kind %d", i, d.kind);
+        }
+    }
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (o->device < 0 || o->device >= ndev) return fail(DN_EINVAL, "device %d not present (%d devices)", o->device, ndev);
+    HIPCHK(hipSetDevice(o->device));
+    dn_net *net = new (std::nothrow) dn_net();
+    if (!net) return fail(DN_ENOMEM, "out of host memory");
+    net->L.assign(layers, layers + n);
+    net->o = *o;
+    net->cw.resize(n);
+    net->in_c = chans;
+    net->scale.assign(n + 1, 1.0f);
+    if (hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete net;
+        return fail(DN_EHIP, "hipStreamCreate failed");
+    }
+    // shape check against the largest input
+    Plan p;
+    dn_status st = make_plan(net, o->dtype, o->mode, 1, o->max_h, o->max_w, &p);
+    if (st != DN_OK) {
+        dn_net_destroy(net);
+        return st;
+    }
+    *out = net;
+    return DN_OK;
+}
+
+static void free_weights(ConvWeights &cw)
+{
+    if (cw.w) (void)hipFree(cw.w);
+    if (cw.bias) (void)hipFree(cw.bias);
+    if (cw.wscale) (void)hipFree(cw.wscale);
+    if (cw.w32) (void)hipFree(cw.w32);
+    if (cw.bias32) (void)hipFree(cw.bias32);
+    if (cw.wscale32) (void)hipFree(cw.wscale32);
+    if (cw.pinned) (void)hipHostFree(cw.pinned);
+    cw = ConvWeights();
+}
+
+extern "C" void dn_net_destroy(dn_net *net)
+{
+    if (!net) return;
+    (void)hipSetDevice(net->o.device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &cw : net->cw) free_weights(cw);
+    for (auto &kv : net->host_vals)
+        for (unsigned char *b : kv.second) (void)hipHostFree(b);
+    if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
+    delete net;
+}
+
+extern "C" dn_status dn_net_output_shape(const dn_net *net, int h, int w, int *c, int *ho, int *wo)
+{
+    if (!net || !c || !ho || !wo) return fail(DN_EINVAL, "NULL argument");
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, net->o.mode, 1, h, w, &p));
+    const Value &v = p.vals[p.out_val];
+    *c = v.c; *ho = v.h; *wo = v.w;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_arena_bytes(const dn_net *net, int batch, int h, int w, size_t *bytes)
+{
+    if (!net || !bytes) return fail(DN_EINVAL, "NULL argument");
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, net->o.mode, batch, h, w, &p));
+    *bytes = p.total;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_bind_arena(dn_net *net, void *dev_ptr, size_t bytes)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (!dev_ptr || bytes == 0) return fail(DN_EINVAL, "arena pointer/size missing");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(DN_EINVAL, "arena must be 256-byte aligned");
+    if (!is_device_ptr(dev_ptr)) return fail(DN_EINVAL, "arena is not device memory");
+    std::lock_guard<std::mutex> g(net->mu);
+    net->arena = dev_ptr;
+    net->arena_bytes = bytes;
+    return DN_OK;
+}
+
+static dn_status pack_to(dn_net *net, int layer, int dt, const double *dw, const double *db, const double *dm,
+                         const double *dv, const double *dg, const double *dbe, int has_bn, void **w, float **b,
+                         float **s, hipStream_t st)
+{
+    ConvWeights &cw = net->cw[layer];
+    const dn_layer_desc &d = net->L[layer];
+    const int cin_p = cpad(dt, cw.cin);
+    const int K = d.ksize * d.ksize * cin_p;
+    const int k_pad = (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const int cout_p = cpad(dt, d.cout);
+    const size_t wb = (size_t)cout_p * k_pad * esize(dt);
+    HIPCHK(hipMalloc(w, wb));
+    HIPCHK(hipMalloc((void **)b, cout_p * sizeof(float)));
+    HIPCHK(hipMalloc((void **)s, cout_p * sizeof(float)));
+    HIPCHK(launch_fold_pack(dt, dw, db, dm, dv, dg, dbe, net->o.bn_eps, has_bn, d.cout, cw.cin, d.ksize, d.ksize,
+                            cin_p, k_pad, cout_p, *w, *b, *s, st));
+    if (w == &cw.w) {
+        cw.cin_p = cin_p; cw.cout = d.cout; cw.cout_p = cout_p; cw.k_pad = k_pad; cw.wbytes = wb;
+    } else {
+        cw.k_pad32 = k_pad;
+    }
+    return DN_OK;
+}
+
+extern "C" dn_status dn_load_weights(dn_net *net, int layer, const double *w, const double *bias, const double *mean,
+                                     const double *var, const double *gamma, const double *beta)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (layer < 0 || layer >= (int)net->L.size() || net->L[layer].kind != DN_CONV)
+        return fail(DN_EINVAL, "layer %d is not a conv layer", layer);
+    const dn_layer_desc &d = net->L[layer];
+    if (!w || !bias) return fail(DN_EINVAL, "conv layer %d: w and bias are required", layer);
+    const bool any_bn = mean || var || gamma || beta;
+    const bool all_bn = mean && var && gamma && beta;
+    if (d.batchnorm ? !all_bn : any_bn)
+        return fail(DN_EINVAL, "conv layer %d: BN arrays must be all present iff the layer has batchnorm", layer);
+    std::lock_guard<std::mutex> g(net->mu);
+    HIPCHK(hipSetDevice(net->o.device));
+    ConvWeights &cw = net->cw[layer];
+    free_weights(cw);
+    cw.cin = net->in_c[layer];
+    const size_t nw = (size_t)d.cout * cw.cin * d.ksize * d.ksize;
+    const size_t nvec = d.cout;
+    double *dbuf = nullptr;
+    const size_t tot = nw + 5 * nvec;
+    HIPCHK(hipMalloc(&dbuf, tot * sizeof(double)));
+    double *dw = dbuf, *db = dbuf + nw, *dm = db + nvec, *dv = dm + nvec, *dg = dv + nvec, *dbe = dg + nvec;
+    hipStream_t st = net->cap_stream;
+    dn_status rc = DN_OK;
+    auto cp = [&](double *dst, const double *src, size_t n) -> bool {
+        return hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+    };
+    bool ok = cp(dw, w, nw) && cp(db, bias, nvec);
+    if (ok && d.batchnorm) ok = cp(dm, mean, nvec) && cp(dv, var, nvec) && cp(dg, gamma, nvec) && cp(dbe, beta, nvec);
+    if (!ok) rc = fail(DN_EHIP, "weight upload failed: %s", hipGetErrorString(hipGetLastError()));
+    if (rc == DN_OK)
+        rc = pack_to(net, layer, net->o.dtype, dw, db, dm, dv, dg, dbe, d.batchnorm, &cw.w, &cw.bias, &cw.wscale, st);
+    if (rc == DN_OK && net->o.dtype == DN_FP8_E4M3)
+        rc = pack_to(net, layer, F32, dw, db, dm, dv, dg, dbe, d.batchnorm, &cw.w32, &cw.bias32, &cw.wscale32, st);
+    if (rc == DN_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(DN_EHIP, "weight fold/pack failed");
+    (void)hipFree(dbuf);
+    if (rc != DN_OK) {
+        free_weights(cw);
+        return rc;
+    }
+    if (net->o.mode == DN_MODE_PER_LAYER) {
+        // host copy of the packed weights: the per-layer mode re-uploads them around every layer
+        const size_t vb = (size_t)cw.cout_p * sizeof(float);
+        if (hipHostMalloc(&cw.pinned, cw.wbytes + 2 * vb, hipHostMallocDefault) != hipSuccess) {
+            free_weights(cw);
+            return fail(DN_ENOMEM, "pinned host weights");
+        }
+        char *hp = (char *)cw.pinned;
+        if (hipMemcpy(hp, cw.w, cw.wbytes, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(hp + cw.wbytes, cw.bias, vb, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(hp + cw.wbytes + vb, cw.wscale, vb, hipMemcpyDeviceToHost) != hipSuccess) {
+            free_weights(cw);
+            return fail(DN_EHIP, "weight readback failed");
+        }
+    }
+    cw.loaded = true;
+    net->calibrated = false;
+    for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
+    net->graphs.clear();
+    return DN_OK;
+}
+
+static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, const void *x, int batch, int h,
+                                  int w, void *y, hipStream_t s)
+{
+    STCHK(check_ready(net, true));
+    STCHK(check_dims(net, batch, h, w));
+    if (!x || !y) return fail(DN_EINVAL, "x/y are NULL");
+    if (!arena) return fail(DN_ESTATE, "no arena bound");
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
+    if (arena_bytes < p.total) return fail(DN_ENOMEM, "arena has %zu bytes, plan needs %zu", arena_bytes, p.total);
+    if (!net->o.use_graph) return enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, s);
+    GraphKey key{batch, h, w, x, y, arena};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> g(net->mu);
+        auto it = net->graphs.find(key);
+        if (it != net->graphs.end()) exec = it->second;
+    }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
+        dn_status rc = enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, net->cap_stream);
+        hipError_t e = hipStreamEndCapture(net->cap_stream, &graph);
+        if (rc != DN_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(DN_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(DN_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        std::lock_guard<std::mutex> g(net->mu);
+        net->graphs[key] = exec;
+    }
+    HIPCHK(hipGraphLaunch(exec, s));
+    return DN_OK;
+}
+
+// Naive offload baseline: every layer's input, weights and output cross PCIe
+// around its own kernel, with a full synchronisation per layer.
+static dn_status forward_per_layer(dn_net *net, const void *x, int batch, int h, int w, void *y, hipStream_t s)
+{
+    STCHK(check_ready(net, true));
+    STCHK(check_dims(net, batch, h, w));
+    if (!x || !y) return fail(DN_EINVAL, "x/y are NULL");
+    if (!net->arena) return fail(DN_ESTATE, "no arena bound");
+    if (is_device_ptr(x) || is_device_ptr(y)) return fail(DN_EINVAL, "per-layer mode takes host x/y");
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_PER_LAYER, batch, h, w, &p));
+    if (net->arena_bytes < p.total) return fail(DN_ENOMEM, "arena has %zu bytes, plan needs %zu", net->arena_bytes, p.total);
+    char *base = (char *)net->arena;
+    // host-side copy of every activation (the CPU-resident data of a naive offload)
+    std::vector<unsigned char *> *hv;
+    {
+        std::lock_guard<std::mutex> g(net->mu);
+        auto key = std::make_tuple(batch, h, w);
+        hv = &net->host_vals[key];
+        if (hv->empty()) {
+            for (const Value &v : p.vals) {
+                unsigned char *b = nullptr;
+                if (hipHostMalloc((void **)&b, v.bytes, hipHostMallocDefault) != hipSuccess) {
+                    for (unsigned char *q : *hv) (void)hipHostFree(q);
+                    hv->clear();
+                    return fail(DN_ENOMEM, "pinned host activations");
+                }
+                hv->push_back(b);
+            }
+        }
+    }
+    const Value &v0 = p.vals[0];
+    const size_t xbytes = (size_t)batch * v0.c * h * w * 4;
+    // input: host -> device, ingest, device -> host
+    HIPCHK(hipMemcpyAsync(base + p.xin_off, x, xbytes, hipMemcpyHostToDevice, s));
+    const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
+    HIPCHK(launch_ingest(p.dtype, (const float *)(base + p.xin_off), batch, v0.c, h, w, v0.cp, in_inv, base + v0.off, s));
+    HIPCHK(hipMemcpyAsync((*hv)[0], base + v0.off, v0.bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (const Op &op : p.ops) {
+        HIPCHK(hipMemcpyAsync(base + p.vals[op.in].off, (*hv)[op.in], p.vals[op.in].bytes, hipMemcpyHostToDevice, s));
+        if (op.in2 >= 0)
+            HIPCHK(hipMemcpyAsync(base + p.vals[op.in2].off, (*hv)[op.in2], p.vals[op.in2].bytes, hipMemcpyHostToDevice, s));
+        if (op.kind == OP_CONV) {
+            ConvWeights &cw = net->cw[op.conv];
+            const size_t vb = (size_t)cw.cout_p * sizeof(float);
+            const char *hp = (const char *)cw.pinned;
+            HIPCHK(hipMemcpyAsync(cw.w, hp, cw.wbytes, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(cw.bias, hp + cw.wbytes, vb, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(cw.wscale, hp + cw.wbytes + vb, vb, hipMemcpyHostToDevice, s));
+        }
+        STCHK(enqueue_op(net, p, op, base, s, false));
+        HIPCHK(hipMemcpyAsync((*hv)[op.out], base + p.vals[op.out].off, p.vals[op.out].bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    const Value &vo = p.vals[p.out_val];
+    HIPCHK(hipMemcpyAsync(base + vo.off, (*hv)[p.out_val], vo.bytes, hipMemcpyHostToDevice, s));
+    const float osc = p.dtype == FP8 ? net->scale[p.out_val] : 1.0f;
+    HIPCHK(launch_egress(p.dtype, base + vo.off, batch, vo.c, vo.h, vo.w, vo.cp, osc, (float *)(base + p.yout_off), s));
+    HIPCHK(hipMemcpyAsync(y, base + p.yout_off, (size_t)batch * vo.c * vo.h * vo.w * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_forward(dn_net *net, const void *x, int batch, int h, int w, void *y, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (hipSetDevice(net->o.device) != hipSuccess) return fail(DN_EHIP, "hipSetDevice");
+    if (net->o.mode == DN_MODE_PER_LAYER) return forward_per_layer(net, x, batch, h, w, y, (hipStream_t)stream);
+    return forward_resident(net, net->arena, net->arena_bytes, x, batch, h, w, y, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_forward_arena(dn_net *net, void *arena, size_t arena_bytes, const void *x, int batch, int h,
+                                      int w, void *y, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (net->o.mode != DN_MODE_RESIDENT) return fail(DN_EUNSUPPORTED, "dn_forward_arena needs a resident-mode net");
+    if (!arena || ((uintptr_t)arena & 255)) return fail(DN_EINVAL, "arena missing or not 256-byte aligned");
+    if (hipSetDevice(net->o.device) != hipSuccess) return fail(DN_EHIP, "hipSetDevice");
+    return forward_resident(net, arena, arena_bytes, x, batch, h, w, y, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h, int w, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (net->o.dtype != DN_FP8_E4M3) return fail(DN_EINVAL, "dn_calibrate is for FP8 nets");
+    STCHK(check_ready(net, false));
+    STCHK(check_dims(net, batch, h, w));
+    if (!x || !is_device_ptr(x)) return fail(DN_EINVAL, "calibration input must be device memory");
+    HIPCHK(hipSetDevice(net->o.device));
+    hipStream_t s = (hipStream_t)stream;
+    // FP32 forward over the unfused layer list (each layer's own tensor gets a scale)
+    Plan p;
+    STCHK(make_plan(net, F32, DN_MODE_PER_LAYER, batch, h, w, &p));
+    char *base = nullptr;
+    const size_t nv = p.vals.size();
+    HIPCHK(hipMalloc(&base, p.total + align256(nv * sizeof(float))));
+    float *amax = (float *)(base + p.total);
+    dn_status rc = DN_OK;
+    auto run = [&]() -> dn_status {
+        HIPCHK(launch_zero_f32(amax, nv, s));
+        const Value &v0 = p.vals[0];
+        HIPCHK(launch_ingest(F32, x, batch, v0.c, h, w, v0.cp, 1.0f, base + v0.off, s));
+        HIPCHK(launch_amax((const float *)(base + v0.off), (size_t)batch * h * w * v0.cp, amax, s));
+        for (const Op &op : p.ops) {
+            STCHK(enqueue_op(net, p, op, base, s, true));
+            const Value &vo = p.vals[op.out];
+            HIPCHK(launch_amax((const float *)(base + vo.off), (size_t)batch * vo.h * vo.w * vo.cp, amax + op.out, s));
+        }
+        std::vector<float> hm(nv);
+        HIPCHK(hipMemcpyAsync(hm.data(), amax, nv * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t v = 0; v < nv; ++v) net->scale[v] = hm[v] > 0.f ? hm[v] / 448.0f : 1.0f;
+        // a max pool only selects values: its output keeps its input's scale
+        for (size_t i = 0; i < net->L.size(); ++i)
+            if (net->L[i].kind == DN_MAXPOOL) net->scale[i + 1] = net->scale[i];
+        return DN_OK;
+    };
+    rc = run();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+    if (rc == DN_OK) {
+        std::lock_guard<std::mutex> g(net->mu);
+        net->calibrated = true;
+        for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
+        net->graphs.clear();
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+static void load_tune_cache(dn_net *net)
+{
+    const char *path = getenv("DN_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int t, s;
+    while (fscanf(f, "%255s %d %d", key, &t, &s) == 3)
+        if (t >= 0 && t < tile_count() && s >= 1) net->tuned[key] = {t, s};
+    fclose(f);
+}
+
+static void save_tune_cache(const dn_net *net)
+{
+    const char *path = getenv("DN_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : net->tuned) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    fclose(f);
+}
+
+static bool tile_fits(int tile, int cout_p)
+{
+    const TileCfg t = tile_cfg(tile);
+    // avoid tiles whose N extent is more than 4x the layer width (pure waste)
+    return t.bn <= std::max(16, cout_p) * 4 && t.bn <= std::max(cout_p, 16) * 2;
+}
+
+extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (net->o.mode != DN_MODE_RESIDENT) return fail(DN_EUNSUPPORTED, "autotune runs on resident-mode nets");
+    STCHK(check_ready(net, true));
+    STCHK(check_dims(net, batch, h, w));
+    if (!net->arena) return fail(DN_ESTATE, "no arena bound");
+    HIPCHK(hipSetDevice(net->o.device));
+    hipStream_t s = (hipStream_t)stream;
+    load_tune_cache(net);
+    // plan with the largest split-K candidate so the scratch region is big enough
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    char *base = (char *)net->arena;
+    dn_status rc = DN_OK;
+    for (const Op &op : p.ops) {
+        if (op.kind != OP_CONV) continue;
+        const dn_layer_desc &d = net->L[op.conv];
+        const std::string sig = conv_sig(p.dtype, op, batch, d.ksize, d.stride);
+        if (net->tuned.count(sig)) continue;
+        const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
+        const int nkt = net->cw[op.conv].k_pad / bk_el(p.dtype);
+        float best = 1e30f;
+        int bt = op.tile, bs = op.splits;
+        for (int t = 0; t < tile_count() && rc == DN_OK; ++t) {
+            if (!tile_fits(t, op.cout_p)) continue;
+            const TileCfg tc = tile_cfg(t);
+            const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
+            for (int sp = 1; sp <= 16 && rc == DN_OK; sp *= 2) {
+                if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
+                const size_t need = sp > 1 ? (size_t)sp * M * op.cout_p * 4 : 0;
+                if (p.ws_off + need > net->arena_bytes) continue;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && rc == DN_OK; ++rep) {  // rep 0 = warm-up
+                    const int iters = rep ? 5 : 1;
+                    if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event");
+                    for (int it = 0; it < iters && rc == DN_OK; ++it) rc = enqueue_op(net, p, op, base, s, false, t, sp);
+                    if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                        rc = fail(DN_EHIP, "tuning launch failed: %s", hipGetErrorString(hipGetLastError()));
+                    if (rc == DN_OK && rep) {
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        ms /= iters;
+                    }
+                }
+                if (rc == DN_OK && ms < best) { best = ms; bt = t; bs = sp; }
+            }
+        }
+        if (rc != DN_OK) break;
+        std::lock_guard<std::mutex> g(net->mu);
+        net->tuned[sig] = {bt, bs};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == DN_OK) {
+        std::lock_guard<std::mutex> g(net->mu);
+        save_tune_cache(net);
+        for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
+        net->graphs.clear();
+    }
+    return rc;
+}
+
+extern "C" dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int h, int w, int *tile, int *splits,
+                                   int *fused_pool, int *fused_res)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
+    for (const Op &op : p.ops) {
+        if (op.kind == OP_CONV && op.conv == layer) {
+            if (tile) *tile = op.tile;
+            if (splits) *splits = op.splits;
+            if (fused_pool) *fused_pool = op.pool;
+            if (fused_res) *fused_res = op.res;
+            return DN_OK;
+        }
+    }
+    return fail(DN_EINVAL, "layer %d is not a conv layer", layer);
+}
+
+extern "C" dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int w, int iters, void *stream, float *avg_ms)
+{
+    if (!net || !avg_ms || iters <= 0) return fail(DN_EINVAL, "bad argument");
+    STCHK(check_ready(net, true));
+    STCHK(check_dims(net, batch, h, w));
+    if (!net->arena) return fail(DN_ESTATE, "no arena bound");
+    HIPCHK(hipSetDevice(net->o.device));
+    Plan p;
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
+    if (net->arena_bytes < p.total) return fail(DN_ENOMEM, "arena too small");
+    const Op *found = nullptr;
+    for (const Op &op : p.ops)
+        if (op.layer == layer || op.conv == layer) found = &op;
+    if (!found) return fail(DN_EINVAL, "no op computes layer %d", layer);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    dn_status rc = DN_OK;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event record");
+    for (int i = 0; i < iters && rc == DN_OK; ++i) rc = enqueue_op(net, p, *found, (char *)net->arena, s, false);
+    if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = fail(DN_EHIP, "timed launches failed");
+    float ms = 0.f;
+    if (rc == DN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    *avg_ms = ms / iters;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// ---------------------------------------------------------------- standalone layers
+
+static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, int *splits, size_t *wbytes,
+                               size_t *vbytes, size_t *wsbytes)
+{
+    if (!d) return fail(DN_EINVAL, "desc is NULL");
+    STCHK(check_dtype(d->dtype));
+    if (d->batch <= 0 || d->in_h <= 0 || d->in_w <= 0 || d->in_c <= 0 || d->cout <= 0 || d->ksize <= 0 ||
+        d->stride <= 0 || d->pad < 0)
+        return fail(DN_EINVAL, "conv desc: non-positive size");
+    if (d->activation != DN_ACT_LINEAR && d->activation != DN_ACT_LEAKY) return fail(DN_EINVAL, "conv desc: activation");
+    if (d->pool != 0 && d->pool != 2) return fail(DN_EUNSUPPORTED, "conv desc: only a fused 2x2 stride-2 pool is supported");
+    if (d->pool && d->residual) return fail(DN_EUNSUPPORTED, "conv desc: pool and residual together");
+    const int dt = d->dtype;
+    const int cin_p = cpad(dt, d->in_c), cout_p = cpad(dt, d->cout);
+    const int Ho = out_side_conv(d->in_h, d->ksize, d->stride, d->pad);
+    const int Wo = out_side_conv(d->in_w, d->ksize, d->stride, d->pad);
+    if (Ho <= 0 || Wo <= 0) return fail(DN_EINVAL, "conv desc: output is empty");
+    if (d->pool && (Ho % 2 || Wo % 2)) return fail(DN_EUNSUPPORTED, "conv desc: fused pool needs an even output (%dx%d)", Ho, Wo);
+    const int K = d->ksize * d->ksize * cin_p;
+    const int k_pad = (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const long Ml = (long)d->batch * Ho * Wo;
+    if (Ml > (1L << 30)) return fail(DN_EUNSUPPORTED, "conv desc: too many output pixels");
+    const int M = (int)Ml;
+    int t = d->tile, sp = d->splits;
+    int ht, hs;
+    heuristic_tile(M, cout_p, k_pad / bk_el(dt), &ht, &hs);
+    if (t < 0) t = ht;
+    if (sp <= 0) sp = (d->tile < 0) ? hs : 1;
+    if (t >= tile_count()) return fail(DN_EINVAL, "tile %d out of range", t);
+    const int nkt = k_pad / bk_el(dt);
+    if (sp > nkt) sp = nkt;
+    if (a) {
+        memset(a, 0, sizeof *a);
+        a->batch = d->batch; a->H = d->in_h; a->W = d->in_w; a->cin_p = cin_p;
+        a->Ho = Ho; a->Wo = Wo; a->cout_p = cout_p;
+        a->R = a->S = d->ksize; a->stride = d->stride; a->pad = d->pad;
+        a->k_pad = k_pad; a->M = M; a->pool = d->pool ? 1 : 0;
+        a->act = d->activation; a->slope = d->leaky_slope;
+        a->in_scale = dt == FP8 ? d->in_scale : 1.0f;
+        a->res_scale = dt == FP8 ? d->res_scale : 1.0f;
+        a->out_inv_scale = dt == FP8 ? 1.0f / d->out_scale : 1.0f;
+        a->splits = sp;
+        a->ktiles_per_split = (nkt + sp - 1) / sp;
+        if (dt == FP8 && !(d->in_scale > 0 && d->out_scale > 0 && (!d->residual || d->res_scale > 0)))
+            return fail(DN_EINVAL, "conv desc: FP8 scales must be positive");
+    }
+    if (tile) *tile = t;
+    if (splits) *splits = sp;
+    if (wbytes) *wbytes = (size_t)cout_p * k_pad * esize(dt);
+    if (vbytes) *vbytes = (size_t)cout_p * sizeof(float);
+    if (wsbytes) *wsbytes = sp > 1 ? (size_t)sp * M * cout_p * sizeof(float) : 0;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_conv_sizes(const dn_conv_desc *d, size_t *w_bytes, size_t *vec_bytes, size_t *ws_bytes)
+{
+    return conv_geometry(d, nullptr, nullptr, nullptr, w_bytes, vec_bytes, ws_bytes);
+}
+
+extern "C" dn_status dn_conv_pack(const dn_conv_desc *d, const double *w, const double *bias, const double *mean,
+                                  const double *var, const double *gamma, const double *beta, double eps,
+                                  void *w_packed, float *bias_out, float *wscale_out, void *stream)
+{
+    size_t wb = 0, vb = 0;
+    STCHK(conv_geometry(d, nullptr, nullptr, nullptr, &wb, &vb, nullptr));
+    if (!w || !bias || !w_packed || !bias_out || !wscale_out) return fail(DN_EINVAL, "conv pack: NULL pointer");
+    const bool any_bn = mean || var || gamma || beta, all_bn = mean && var && gamma && beta;
+    if (any_bn && !all_bn) return fail(DN_EINVAL, "conv pack: BN arrays must be all present or all NULL");
+    if (all_bn && !(eps > 0)) return fail(DN_EINVAL, "conv pack: eps must be > 0");
+    const int dt = d->dtype;
+    const int cin_p = cpad(dt, d->in_c), cout_p = cpad(dt, d->cout);
+    const int k_pad = (int)(wb / esize(dt) / cout_p);
+    const size_t nw = (size_t)d->cout * d->in_c * d->ksize * d->ksize, nv = d->cout;
+    hipStream_t s = (hipStream_t)stream;
+    double *buf = nullptr;
+    HIPCHK(hipMalloc(&buf, (nw + 6 * nv) * sizeof(double)));
+    double *dw = buf, *db = buf + nw, *dm = db + nv, *dv = dm + nv, *dg = dv + nv, *dbe = dg + nv;
+    dn_status rc = DN_OK;
+    auto cp = [&](double *dst, const double *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = cp(dw, w, nw) && cp(db, bias, nv);
+    if (ok && all_bn) ok = cp(dm, mean, nv) && cp(dv, var, nv) && cp(dg, gamma, nv) && cp(dbe, beta, nv);
+    if (!ok) rc = fail(DN_EHIP, "conv pack upload failed");
+    if (rc == DN_OK && launch_fold_pack(dt, dw, db, dm, dv, dg, dbe, eps, all_bn ? 1 : 0, d->cout, d->in_c, d->ksize,
+                                        d->ksize, cin_p, k_pad, cout_p, w_packed, bias_out, wscale_out, s) != hipSuccess)
+        rc = fail(DN_EHIP, "fold/pack launch failed");
+    if (hipStreamSynchronize(s) != hipSuccess && rc == DN_OK) rc = fail(DN_EHIP, "fold/pack failed");
+    (void)hipFree(buf);
+    return rc;
+}
+
+extern "C" dn_status dn_conv2d(const dn_conv_desc *d, const void *x, const void *w_packed, const float *bias,
+                               const float *wscale, const void *res, void *y, void *workspace, size_t ws_bytes,
+                               void *stream)
+{
+    ConvArgs a;
+    int tile = 0, splits = 1;
+    size_t need = 0;
+    STCHK(conv_geometry(d, &a, &tile, &splits, nullptr, nullptr, &need));
+    if (!x || !w_packed || !bias || !y) return fail(DN_EINVAL, "conv2d: NULL pointer");
+    if (d->dtype == DN_FP8_E4M3 && !wscale) return fail(DN_EINVAL, "conv2d: FP8 needs wscale");
+    if (d->residual && !res) return fail(DN_EINVAL, "conv2d: residual requested without res");
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(DN_EINVAL, "conv2d: split-K %d needs %zu workspace bytes (%zu given)", splits, need, ws_bytes);
+    a.x = x; a.w = w_packed; a.bias = bias; a.wscale = wscale;
+    a.res = d->residual ? res : nullptr;
+    a.y = y;
+    a.partial = (float *)workspace;
+    HIPCHK(launch_conv(d->dtype, tile, a, (hipStream_t)stream));
+    if (splits > 1) HIPCHK(launch_splitk_reduce(d->dtype, a, (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_maxpool(const dn_pool_desc *d, const void *x, void *y, void *stream)
+{
+    if (!d || !x || !y) return fail(DN_EINVAL, "maxpool: NULL argument");
+    STCHK(check_dtype(d->dtype));
+    if (d->batch <= 0 || d->h <= 0 || d->w <= 0 || d->c <= 0 || d->size <= 0 || d->stride <= 0)
+        return fail(DN_EINVAL, "maxpool: non-positive size");
+    const int cp = cpad(d->dtype, d->c);
+    HIPCHK(launch_maxpool(d->dtype, x, y, d->batch, d->h, d->w, cp, d->size, d->stride, out_side_pool(d->h, d->stride),
+                          out_side_pool(d->w, d->stride), (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_shortcut(int dtype, size_t count, const void *a, float sa, const void *b, float sb, void *y,
+                                 float sy, void *stream)
+{
+    STCHK(check_dtype(dtype));
+    if (!a || !b || !y) return fail(DN_EINVAL, "shortcut: NULL argument");
+    if (count % seg_el(dtype)) return fail(DN_EINVAL, "shortcut: count must be a multiple of %d", seg_el(dtype));
+    if (dtype == DN_FP8_E4M3 && !(sa > 0 && sb > 0 && sy > 0)) return fail(DN_EINVAL, "shortcut: FP8 scales must be positive");
+    const bool f8 = dtype == DN_FP8_E4M3;
+    HIPCHK(launch_add(dtype, a, f8 ? sa : 1.f, b, f8 ? sb : 1.f, y, f8 ? 1.0f / sy : 1.f, count, (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, float scale, void *y,
+                               void *stream)
+{
+    STCHK(check_dtype(dtype));
+    if (!x || !y || batch <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "ingest: bad argument");
+    if (dtype == DN_FP8_E4M3 && !(scale > 0)) return fail(DN_EINVAL, "ingest: FP8 scale must be positive");
+    HIPCHK(launch_ingest(dtype, x, batch, c, h, w, cpad(dtype, c), dtype == DN_FP8_E4M3 ? 1.0f / scale : 1.0f, y,
+                         (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale, float *y,
+                               void *stream)
+{
+    STCHK(check_dtype(dtype));
+    if (!x || !y || batch <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "egress: bad argument");
+    HIPCHK(launch_egress(dtype, x, batch, c, h, w, cpad(dtype, c), dtype == DN_FP8_E4M3 ? scale : 1.0f, y,
+                         (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" int dn_tile_count(void) { return tile_count(); }
+
+extern "C" dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n)
+{
+    if (tile < 0 || tile >= tile_count()) return fail(DN_EINVAL, "tile %d out of range", tile);
+    const TileCfg t = tile_cfg(tile);
+    if (bm) *bm = t.bm;
+    if (bn) *bn = t.bn;
+    if (waves_m) *waves_m = t.wm;
+    if (waves_n) *waves_n = t.wn;
+    return DN_OK;
+}

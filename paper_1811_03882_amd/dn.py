@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libdn.so (include/dn.h): argument marshalling only.
+
+Every step of the forward pass runs in the library's HIP kernels.  PyTorch is
+used by callers only to own device memory (pass a tensor, its data_ptr() is
+taken) and streams (pass a torch stream, its handle is taken).  If libdn.so
+is missing this module raises at import time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdn.so")
+
+DN_OK, DN_EINVAL, DN_ENOMEM, DN_EHIP, DN_ESTATE, DN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+F32, BF16, FP8 = 0, 1, 2
+RESIDENT, PER_LAYER = 0, 1
+CONV, MAXPOOL, SHORTCUT = 0, 1, 2
+LINEAR, LEAKY = 0, 1
+DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "fp8": FP8, "fp8_e4m3": FP8}
+ESIZE = {F32: 4, BF16: 2, FP8: 1}
+FP8_MAX = 448.0
+
+
+class DnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("dn error %d: %s" % (status, msg))
+        self.status = status
+
+
+class LayerDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("cout", ctypes.c_int), ("ksize", ctypes.c_int),
+                ("stride", ctypes.c_int), ("pad", ctypes.c_int), ("batchnorm", ctypes.c_int),
+                ("activation", ctypes.c_int), ("src", ctypes.c_int)]
+
+
+class NetOpts(ctypes.Structure):
+    _fields_ = [("in_c", ctypes.c_int), ("max_h", ctypes.c_int), ("max_w", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("dtype", ctypes.c_int), ("mode", ctypes.c_int),
+                ("leaky_slope", ctypes.c_float), ("bn_eps", ctypes.c_double),
+                ("use_graph", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class ConvDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("in_h", ctypes.c_int), ("in_w", ctypes.c_int),
+                ("in_c", ctypes.c_int), ("cout", ctypes.c_int), ("ksize", ctypes.c_int),
+                ("stride", ctypes.c_int), ("pad", ctypes.c_int), ("activation", ctypes.c_int),
+                ("leaky_slope", ctypes.c_float), ("pool", ctypes.c_int), ("residual", ctypes.c_int),
+                ("dtype", ctypes.c_int), ("in_scale", ctypes.c_float), ("res_scale", ctypes.c_float),
+                ("out_scale", ctypes.c_float), ("tile", ctypes.c_int), ("splits", ctypes.c_int)]
+
+
+class PoolDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("h", ctypes.c_int), ("w", ctypes.c_int), ("c", ctypes.c_int),
+                ("size", ctypes.c_int), ("stride", ctypes.c_int), ("dtype", ctypes.c_int)]
+
+
+_vp, _i, _sz, _f, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_float, ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+SIGNATURES = {
+    "dn_net_create": (_i, [ctypes.POINTER(LayerDesc), _i, ctypes.POINTER(NetOpts), ctypes.POINTER(_vp)]),
+    "dn_net_destroy": (None, [_vp]),
+    "dn_net_output_shape": (_i, [_vp, _i, _i, _ip, _ip, _ip]),
+    "dn_arena_bytes": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "dn_bind_arena": (_i, [_vp, _vp, _sz]),
+    "dn_load_weights": (_i, [_vp, _i, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "dn_calibrate": (_i, [_vp, _vp, _i, _i, _i, _vp]),
+    "dn_forward": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_forward_arena": (_i, [_vp, _vp, _sz, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_autotune": (_i, [_vp, _i, _i, _i, _vp]),
+    "dn_time_layer": (_i, [_vp, _i, _i, _i, _i, _i, _vp, ctypes.POINTER(_f)]),
+    "dn_layer_plan": (_i, [_vp, _i, _i, _i, _i, _ip, _ip, _ip, _ip]),
+    "dn_channel_pad": (_i, [_i, _i]),
+    "dn_conv_sizes": (_i, [ctypes.POINTER(ConvDesc), ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    "dn_conv_pack": (_i, [ctypes.POINTER(ConvDesc), _dp, _dp, _dp, _dp, _dp, _dp, _d, _vp, _vp, _vp, _vp]),
+    "dn_conv2d": (_i, [ctypes.POINTER(ConvDesc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "dn_maxpool": (_i, [ctypes.POINTER(PoolDesc), _vp, _vp, _vp]),
+    "dn_shortcut": (_i, [_i, _sz, _vp, _f, _vp, _f, _vp, _f, _vp]),
+    "dn_ingest": (_i, [_i, _i, _i, _i, _i, _vp, _f, _vp, _vp]),
+    "dn_egress": (_i, [_i, _i, _i, _i, _i, _vp, _f, _vp, _vp]),
+    "dn_tile_count": (_i, []),
+    "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip]),
+    "dn_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdn.so not built at %s (run python -m paper_1811_03882_amd.build)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def last_error() -> str:
+    m = LIB.dn_last_error()
+    return m.decode() if m else ""
+
+
+def check(status: int) -> None:
+    if status != DN_OK:
+        raise DnError(status, last_error())
+
+
+def ptr(x) -> Optional[int]:
+    """Device/host address of a torch tensor, numpy array or int (None stays None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError("cannot take the address of %r" % type(x))
+
+
+def stream_handle(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _dptr(a):
+    import numpy as np
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return arr, arr.ctypes.data_as(_dp)
+
+
+def channel_pad(dtype: int, c: int) -> int:
+    return LIB.dn_channel_pad(dtype, c)
+
+
+def tile_count() -> int:
+    return LIB.dn_tile_count()
+
+
+def tile_info(t: int) -> Tuple[int, int, int, int]:
+    v = [_i() for _ in range(4)]
+    check(LIB.dn_tile_info(t, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def layer_descs(layers) -> "ctypes.Array":
+    arr = (LayerDesc * len(layers))()
+    for i, L in enumerate(layers):
+        arr[i] = LayerDesc(L.kind, L.cout, L.ksize, L.stride, L.pad, int(bool(L.batchnorm)),
+                           L.activation, L.src)
+    return arr
+
+
+class Net:
+    """A network in the library (dn_net), created from layer objects with the
+    fields kind, cout, ksize, stride, pad, batchnorm, activation, src."""
+
+    def __init__(self, layers: Sequence, in_c: int, max_h: int, max_w: int, max_batch: int,
+                 dtype: int = F32, mode: int = RESIDENT, leaky_slope: float = 0.1,
+                 bn_eps: float = 1e-5, use_graph: bool = False, device: int = 0):
+        self.layers = list(layers)
+        self.dtype, self.mode = dtype, mode
+        self.in_c = in_c
+        opts = NetOpts(in_c, max_h, max_w, max_batch, dtype, mode, leaky_slope, bn_eps,
+                       int(bool(use_graph)), device)
+        h = _vp()
+        descs = layer_descs(self.layers)
+        check(LIB.dn_net_create(descs, len(self.layers), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._arena = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            LIB.dn_net_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def output_shape(self, h: int, w: int) -> Tuple[int, int, int]:
+        c, ho, wo = _i(), _i(), _i()
+        check(LIB.dn_net_output_shape(self._h, h, w, ctypes.byref(c), ctypes.byref(ho), ctypes.byref(wo)))
+        return c.value, ho.value, wo.value
+
+    def arena_bytes(self, batch: int, h: int, w: int) -> int:
+        n = _sz()
+        check(LIB.dn_arena_bytes(self._h, batch, h, w, ctypes.byref(n)))
+        return n.value
+
+    def bind_arena(self, arena, nbytes: Optional[int] = None) -> None:
+        if nbytes is None:
+            nbytes = arena.numel() * arena.element_size()
+        check(LIB.dn_bind_arena(self._h, ptr(arena), nbytes))
+        self._arena = arena  # keep the caller's memory alive while bound
+
+    def load_layer(self, layer: int, w, bias, mean=None, var=None, gamma=None, beta=None) -> None:
+        keep = [_dptr(a) for a in (w, bias, mean, var, gamma, beta)]
+        check(LIB.dn_load_weights(self._h, layer, *[k[1] for k in keep]))
+
+    def load_params(self, params) -> None:
+        for i, p in enumerate(params):
+            if p is not None:
+                self.load_layer(i, p.w, p.bias, p.mean, p.var, p.gamma, p.beta)
+
+    def calibrate(self, x, batch: int, h: int, w: int, stream=None) -> None:
+        check(LIB.dn_calibrate(self._h, ptr(x), batch, h, w, stream_handle(stream)))
+
+    def forward(self, x, batch: int, h: int, w: int, y, stream=None) -> None:
+        check(LIB.dn_forward(self._h, ptr(x), batch, h, w, ptr(y), stream_handle(stream)))
+
+    def forward_arena(self, arena, nbytes: int, x, batch: int, h: int, w: int, y, stream=None) -> None:
+        check(LIB.dn_forward_arena(self._h, ptr(arena), nbytes, ptr(x), batch, h, w, ptr(y),
+                                   stream_handle(stream)))
+
+    def autotune(self, batch: int, h: int, w: int, stream=None) -> None:
+        check(LIB.dn_autotune(self._h, batch, h, w, stream_handle(stream)))
+
+    def time_layer(self, layer: int, batch: int, h: int, w: int, iters: int, stream=None) -> float:
+        ms = _f()
+        check(LIB.dn_time_layer(self._h, layer, batch, h, w, iters, stream_handle(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def layer_plan(self, layer: int, batch: int, h: int, w: int):
+        v = [_i() for _ in range(4)]
+        check(LIB.dn_layer_plan(self._h, layer, batch, h, w, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("tile", "splits", "fused_pool", "fused_res"), (x.value for x in v)))
+
+
+# ------------------------------------------------------------ standalone layers
+
+
+def conv_desc(batch, in_h, in_w, in_c, cout, ksize, stride, pad, activation=LEAKY, slope=0.1,
+              pool=0, residual=0, dtype=F32, in_scale=1.0, res_scale=1.0, out_scale=1.0,
+              tile=-1, splits=0) -> ConvDesc:
+    return ConvDesc(batch, in_h, in_w, in_c, cout, ksize, stride, pad, activation, slope, pool,
+                    residual, dtype, in_scale, res_scale, out_scale, tile, splits)
+
+
+def conv_sizes(d: ConvDesc) -> Tuple[int, int, int]:
+    a, b, c = _sz(), _sz(), _sz()
+    check(LIB.dn_conv_sizes(ctypes.byref(d), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def conv_pack(d: ConvDesc, w, bias, mean, var, gamma, beta, eps, w_out, bias_out, wscale_out, stream=None):
+    keep = [_dptr(a) for a in (w, bias, mean, var, gamma, beta)]
+    check(LIB.dn_conv_pack(ctypes.byref(d), *[k[1] for k in keep], eps, ptr(w_out), ptr(bias_out),
+                           ptr(wscale_out), stream_handle(stream)))
+
+
+def conv2d(d: ConvDesc, x, w_packed, bias, wscale, res, y, workspace=None, ws_bytes=0, stream=None):
+    check(LIB.dn_conv2d(ctypes.byref(d), ptr(x), ptr(w_packed), ptr(bias), ptr(wscale), ptr(res), ptr(y),
+                        ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def maxpool(batch, h, w, c, size, stride, dtype, x, y, stream=None):
+    d = PoolDesc(batch, h, w, c, size, stride, dtype)
+    check(LIB.dn_maxpool(ctypes.byref(d), ptr(x), ptr(y), stream_handle(stream)))
+
+
+def shortcut(dtype, count, a, sa, b, sb, y, sy, stream=None):
+    check(LIB.dn_shortcut(dtype, count, ptr(a), sa, ptr(b), sb, ptr(y), sy, stream_handle(stream)))
+
+
+def ingest(dtype, batch, c, h, w, x, scale, y, stream=None):
+    check(LIB.dn_ingest(dtype, batch, c, h, w, ptr(x), scale, ptr(y), stream_handle(stream)))
+
+
+def egress(dtype, batch, c, h, w, x, scale, y, stream=None):
+    check(LIB.dn_egress(dtype, batch, c, h, w, ptr(x), scale, ptr(y), stream_handle(stream)))

@@ -1,0 +1,209 @@
+"""GPU parity of whole-network forwards (C ABI via the binding) against the FP64
+oracle on the seeded synthetic workloads:
+
+* single conv block, FP32, 1x3x32x32 (end to end, gate 1e-5);
+* 9-layer plain CNN, FP32, batch 1, 416x416, resident and per-layer-transfer
+  modes (end to end 1e-5; the two modes bitwise equal);
+* the same net at batch 64 in BF16 (end to end 2e-2 on sampled images of the
+  full batch, in the hipGraph launch the benchmark times) and FP8 (per-layer
+  gates 6e-2, end-to-end error reported);
+* the 52-conv residual net, BF16, batch 16, 256x256 (sampled images);
+* graph replay == eager, and batch invariance (an image alone == the same
+  image inside a batch).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import net as onet
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    from paper_1811_03882_amd import dn as _dn
+    G.torch_cuda()
+    return _dn
+
+
+def make_net(dn, net, dtype, batch, h, w, mode=0, use_graph=False, seed=1, tune=False):
+    torch = G.torch_cuda()
+    n = dn.Net(net.layers, net.in_c, h, w, batch, dtype=dtype, mode=mode, leaky_slope=net.leaky_slope,
+               bn_eps=net.bn_eps, use_graph=use_graph)
+    n.load_params(synth.make_params(net, seed))
+    if dtype == dn.FP8:
+        xc = G.dev(synth.make_input(net, min(batch, 4), synth.SEED_CALIB, h=h, w=w).astype(np.float32))
+        n.calibrate(xc, xc.shape[0], h, w)
+    arena = G.empty_bytes(n.arena_bytes(batch, h, w) * (2 if tune else 1))
+    n.bind_arena(arena)
+    if tune:
+        n.autotune(batch, h, w)
+        need = n.arena_bytes(batch, h, w)
+        assert need <= arena.numel()
+    torch.cuda.synchronize()
+    return n
+
+
+def gpu_forward(dn, n, x, out_shape, stream=None):
+    torch = G.torch_cuda()
+    xd = G.dev(x.astype(np.float32))
+    y = torch.empty((x.shape[0],) + out_shape, dtype=torch.float32, device="cuda")
+    n.forward(xd, x.shape[0], x.shape[2], x.shape[3], y, stream)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64)
+
+
+def test_single_block_f32(dn):
+    net = synth.single_block()
+    x = synth.make_input(net, 1, synth.SEED_SINGLE)
+    ref = onet.forward(net, synth.make_params(net, synth.SEED_SINGLE), x)[-1]
+    n = make_net(dn, net, dn.F32, 1, 32, 32, seed=synth.SEED_SINGLE)
+    got = gpu_forward(dn, n, x, n.output_shape(32, 32))
+    err = G.rel_l2(got, ref)
+    print("single block f32 rel_l2 = %.3e" % err)
+    assert got.shape == (1, 16, 16, 16)
+    assert err < 1e-5
+
+
+def test_plain9_f32_b1_resident_and_per_layer(dn):
+    net = synth.plain9()
+    x = synth.make_input(net, 1, synth.SEED_PLAIN)
+    outs = onet.forward(net, synth.make_params(net, synth.SEED_PLAIN), x)
+    ref = outs[-1]
+    res = make_net(dn, net, dn.F32, 1, 416, 416)
+    got = gpu_forward(dn, res, x, res.output_shape(416, 416))
+    err = G.rel_l2(got, ref)
+    print("plain9 f32 b1 resident rel_l2 = %.3e" % err)
+    assert got.shape == (1, 125, 13, 13)
+    assert err < 1e-5
+    per = make_net(dn, net, dn.F32, 1, 416, 416, mode=dn.PER_LAYER)
+    y = np.empty((1, 125, 13, 13), np.float32)
+    per.forward(np.ascontiguousarray(x, np.float32), 1, 416, 416, y)
+    np.testing.assert_array_equal(y.astype(np.float64), got)
+
+
+def test_plain9_f32_per_layer_gates(dn):
+    """Each conv layer fed the oracle's own input of that layer (FP32-rounded)."""
+    net = synth.plain9()
+    params = synth.make_params(net, synth.SEED_PLAIN)
+    x = synth.make_input(net, 1, synth.SEED_PLAIN, tag=1, h=128, w=128)
+    outs = onet.forward(net, params, x)
+    ins = [x] + outs[:-1]
+    for i, L in enumerate(net.layers):
+        if L.kind != synth.CONV:
+            continue
+        got = G.run_conv(dn, dn.F32, ins[i], params[i], L.ksize, L.stride, L.pad, L.activation)
+        err = G.rel_l2(got, outs[i])
+        print("layer %d f32 rel_l2 = %.3e" % (i, err))
+        assert err < 1e-5
+
+
+def test_plain9_bf16_b64_graph_sampled(dn):
+    torch = G.torch_cuda()
+    net = synth.plain9()
+    params = synth.make_params(net, synth.SEED_PLAIN)
+    x = synth.make_input(net, 64, synth.SEED_PLAIN)
+    n = make_net(dn, net, dn.BF16, 64, 416, 416, use_graph=True)
+    shape = n.output_shape(416, 416)
+    xd = G.dev(x.astype(np.float32))
+    y = torch.empty((64,) + shape, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    outs = []
+    for rep in range(3):  # graph capture on first call, replays after; eager work in between
+        n.forward(xd, 64, 416, 416, y, s)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    got = outs[0].astype(np.float64)
+    for i in (0, 37, 63):
+        ref = onet.forward(net, params, x[i:i + 1])[-1]
+        err = G.rel_l2(got[i:i + 1], ref)
+        print("plain9 bf16 b64 image %d rel_l2 = %.3e" % (i, err))
+        assert err < 2e-2
+    # graph == eager, and image 5 alone == image 5 in the batch (within the gate)
+    e = make_net(dn, net, dn.BF16, 64, 416, 416, use_graph=False)
+    ye = torch.empty_like(y)
+    e.forward(xd, 64, 416, 416, ye)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ye.cpu().numpy(), outs[0])
+    alone = gpu_forward(dn, e, x[5:6], shape)
+    err = G.rel_l2(alone, got[5:6])
+    print("batch invariance image 5 rel diff = %.3e" % err)
+    assert err < 2e-2
+
+
+def test_plain9_fp8_per_layer_gates_and_end_to_end(dn):
+    net = synth.plain9()
+    params = synth.make_params(net, synth.SEED_PLAIN)
+    x = synth.make_input(net, 2, synth.SEED_PLAIN, tag=2, h=160, w=160)
+    outs = onet.forward(net, params, x)
+    ins = [x] + outs[:-1]
+    for i, L in enumerate(net.layers):
+        if L.kind != synth.CONV:
+            continue
+        got = G.run_conv(dn, dn.FP8, ins[i], params[i], L.ksize, L.stride, L.pad, L.activation,
+                         in_scale=G.fp8_scale(ins[i]), out_scale=G.fp8_scale(outs[i]))
+        err = G.rel_l2(got, outs[i])
+        print("layer %d fp8 rel_l2 = %.3e" % (i, err))
+        assert err < 6e-2
+    n = make_net(dn, net, dn.FP8, 2, 160, 160)
+    got = gpu_forward(dn, n, x, n.output_shape(160, 160))
+    print("plain9 fp8 end-to-end rel_l2 = %.3e (reported, not gated)" % G.rel_l2(got, outs[-1]))
+    assert np.all(np.isfinite(got))
+
+
+def test_residual52_bf16_b16_sampled(dn):
+    net = synth.residual52()
+    params = synth.make_params(net, synth.SEED_RESIDUAL)
+    x = synth.make_input(net, 16, synth.SEED_RESIDUAL)
+    n = make_net(dn, net, dn.BF16, 16, 256, 256, seed=synth.SEED_RESIDUAL, use_graph=True)
+    got = gpu_forward(dn, n, x, n.output_shape(256, 256))
+    assert got.shape == (16, 1024, 8, 8)
+    for i in (0, 15):
+        ref = onet.forward(net, params, x[i:i + 1])[-1]
+        err = G.rel_l2(got[i:i + 1], ref)
+        print("residual52 bf16 b16 image %d rel_l2 = %.3e" % (i, err))
+        assert err < 2e-2
+
+
+def test_residual_f32_small_end_to_end(dn):
+    net = synth.residual52(units=(1, 1, 2, 1, 1), in_hw=64)
+    params = synth.make_params(net, synth.SEED_RESIDUAL)
+    x = synth.make_input(net, 2, synth.SEED_RESIDUAL, tag=3)
+    ref = onet.forward(net, params, x)[-1]
+    n = make_net(dn, net, dn.F32, 2, 64, 64, seed=synth.SEED_RESIDUAL)
+    got = gpu_forward(dn, n, x, n.output_shape(64, 64))
+    err = G.rel_l2(got, ref)
+    print("residual f32 small rel_l2 = %.3e" % err)
+    assert err < 1e-5
+    per = make_net(dn, net, dn.F32, 2, 64, 64, mode=dn.PER_LAYER, seed=synth.SEED_RESIDUAL)
+    y = np.empty(got.shape, np.float32)
+    per.forward(np.ascontiguousarray(x, np.float32), 2, 64, 64, y)
+    np.testing.assert_array_equal(y.astype(np.float64), got)
+
+
+def test_state_errors(dn):
+    net = synth.single_block()
+    n = dn.Net(net.layers, 3, 32, 32, 1)
+    torch = G.torch_cuda()
+    x = torch.zeros((1, 3, 32, 32), device="cuda")
+    y = torch.zeros((1, 16, 16, 16), device="cuda")
+    with pytest.raises(dn.DnError) as e:
+        n.forward(x, 1, 32, 32, y)
+    assert e.value.status == dn.DN_ESTATE  # weights not loaded
+    n.load_params(synth.make_params(net, 0))
+    with pytest.raises(dn.DnError) as e:
+        n.forward(x, 1, 32, 32, y)
+    assert e.value.status == dn.DN_ESTATE  # no arena
+    a = G.empty_bytes(n.arena_bytes(1, 32, 32) // 2)
+    n.bind_arena(a)
+    with pytest.raises(dn.DnError) as e:
+        n.forward(x, 1, 32, 32, y)
+    assert e.value.status == dn.DN_ENOMEM
+    with pytest.raises(dn.DnError) as e:
+        n.forward(x, 2, 32, 32, y)
+    assert e.value.status == dn.DN_EINVAL  # batch above max_batch
