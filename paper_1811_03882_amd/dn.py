@@ -89,6 +89,15 @@ SIGNATURES = {
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64.so (same
+    # SONAME as ROCm's).  Importing torch first makes libdn.so bind to that
+    # already-loaded runtime, so that tensors torch allocates and kernels this
+    # library launches share one device context.  Loading libdn.so first would
+    # pull in a second runtime that cannot open the GPU next to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libdn.so not built at %s (run python -m paper_1811_03882_amd.build)" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)

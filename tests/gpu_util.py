@@ -70,7 +70,7 @@ def run_conv(dn, dtype, x, p, ksize, stride, pad, act, slope=0.1, eps=1e-5, pool
     torch = torch_cuda()
     n, c, h, w = x.shape
     cout = p.w.shape[0]
-    d = dn.conv_desc(n, h, w, c, cout, ksize, stride, pad, act, slope, pool, 1 if res is not None else 0,
+    d = dn.conv_desc(n, h, w, c, cout, ksize, stride, pad, act, slope, 2 if pool else 0, 1 if res is not None else 0,
                      dtype, in_scale, res_scale, out_scale, tile, splits)
     wb, vb, wsb = dn.conv_sizes(d)
     wbuf, bbuf, sbuf = empty_bytes(wb), empty_bytes(vb), empty_bytes(vb)

@@ -93,7 +93,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "b%d_%dx%d_c%d_k%d_r%d_s%d_p%d" % s[:7] + ("_pool" if s[8] else ""))
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8] + ("_pool" if s[8] else ""))
 def test_conv_layer_parity(dn, dtype, shape):
     b, h, w, cin, cout, k, st, pad, pool, act, bn = shape
     p = _params(cout, cin, k, 100 + cin, bn)
