@@ -171,6 +171,9 @@ typedef struct dn_conv_desc {
     float out_scale; /* FP8: y_q = y / out_scale */
     int tile;        /* -1 = library heuristic, else a tile config index */
     int splits;      /* 0 = library heuristic, else split-K factor */
+    int input_nchw;  /* 1: x is the NCHW FP32 network input (ingest fused into the
+                        conv; needs in_c*ksize^2 <= 32 (FP8: 128) and cout <= 64;
+                        weights packed in the order k = (c*ksize + r)*ksize + s) */
 } dn_conv_desc;
 
 /* Bytes of the packed weight buffer, the FP32 bias / weight-scale buffers
@@ -187,7 +190,8 @@ dn_status dn_conv_pack(const dn_conv_desc *d, const double *w, const double *bia
 
 /* Implicit-GEMM convolution (M = batch*Ho*Wo, N = cout, K = k*k*Cin_pad)
  * with the fused epilogue: +bias', activation, [+res], [2x2 max], round.
- * x, y, res, workspace: device.  Enqueue only. */
+ * x, y, res, workspace: device.  Enqueue only.  With input_nchw = 1 the
+ * first-layer kernel runs instead (x = NCHW FP32, no split-K, no residual). */
 dn_status dn_conv2d(const dn_conv_desc *d, const void *x, const void *w_packed,
                     const float *bias, const float *wscale, const void *res, void *y,
                     void *workspace, size_t ws_bytes, void *stream);

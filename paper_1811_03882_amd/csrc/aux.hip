@@ -66,11 +66,12 @@ template <> struct Seg<FP8> {
 // ---------------------------------------------------------------- fold + pack
 // One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
 // w' = w * scale, b' = (b - mean) * scale + beta (b' = b without BN).  The
-// packed row is [k_pad] with k = (r*S + s)*cin_p + c, zeros in every padding.
+// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = (c*R + r)*S + s),
+// zeros in every padding.
 // FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
 
 template <int DT>
-__global__ void __launch_bounds__(256) fold_pack(const double *w, const double *bias, const double *mean,
+__global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, const double *bias, const double *mean,
                                                  const double *var, const double *gamma, const double *beta,
                                                  double eps, int has_bn, int cout, int cin, int R, int S,
                                                  int cin_p, int k_pad, void *wout, float *bout, float *sout)
@@ -87,7 +88,14 @@ __global__ void __launch_bounds__(256) fold_pack(const double *w, const double *
         }
     }
     auto wval = [&](int k) -> double {
-        const int tap = k / cin_p, c = k - tap * cin_p;
+        int c, tap;
+        if (compact) {
+            c = k / RS;
+            tap = k - c * RS;
+        } else {
+            tap = k / cin_p;
+            c = k - tap * cin_p;
+        }
         if (co >= cout || tap >= RS || c >= cin) return 0.0;
         const int r = tap / S, s = tap - r * S;
         return w[(((size_t)co * cin + c) * R + r) * S + s] * sc;
@@ -118,16 +126,16 @@ __global__ void __launch_bounds__(256) fold_pack(const double *w, const double *
     }
 }
 
-hipError_t launch_fold_pack(int dt, const double *w, const double *bias, const double *mean,
+hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta, double eps,
                             int has_bn, int cout, int cin, int R, int S, int cin_p, int k_pad,
                             int cout_p, void *wout, float *bout, float *sout, hipStream_t s)
 {
     dim3 g(cout_p), b(256);
     switch (dt) {
-    case F32: hipLaunchKernelGGL(fold_pack<F32>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
-    case BF16: hipLaunchKernelGGL(fold_pack<BF16>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
-    case FP8: hipLaunchKernelGGL(fold_pack<FP8>, g, b, 0, s, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case F32: hipLaunchKernelGGL(fold_pack<F32>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case BF16: hipLaunchKernelGGL(fold_pack<BF16>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case FP8: hipLaunchKernelGGL(fold_pack<FP8>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -63,7 +63,9 @@ template <> struct Tr<F32> { static constexpr int SPL = 1, KSPT = 2; };
 template <> struct Tr<BF16> { static constexpr int SPL = 1, KSPT = 2; };
 template <> struct Tr<FP8> { static constexpr int SPL = 2, KSPT = 1; };
 
-template <int DT> __device__ __forceinline__ void mma(f4 &acc, const uint4 *a, const uint4 *b)
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int DT> __device__ __forceinline__ void mma(f4 &acc, const u32x4_t *a, const u32x4_t *b)
 {
     if constexpr (DT == F32) {
         const float af[4] = {__uint_as_float(a[0].x), __uint_as_float(a[0].y), __uint_as_float(a[0].z), __uint_as_float(a[0].w)};
@@ -98,6 +100,18 @@ __device__ __forceinline__ float activate(float v, int act, float slope)
 
 // ---------------------------------------------------------------- the kernel
 
+// Global-memory accesses go through explicit address-space-1 pointers so that
+// the compiler emits global (not flat) loads: their completion is tracked by
+// vmcnt alone and the LDS traffic of the current K-tile is not serialised
+// behind the prefetch of the next one.
+#define GLOBAL __attribute__((address_space(1)))
+typedef u32x4_t u32x4;
+
+__device__ __forceinline__ u32x4 gload16(const void *base, size_t byte_off)
+{
+    return *(const GLOBAL u32x4 *)((const GLOBAL char *)base + byte_off);
+}
+
 template <int DT, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 {
@@ -110,8 +124,8 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
     constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
     static_assert(BM % RSTEP == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
 
-    __shared__ uint4 sA[2][BM * 8];
-    __shared__ uint4 sB[2][BN * 8];
+    __shared__ u32x4 sA[2][BM * 8];
+    __shared__ u32x4 sB[2][BN * 8];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -142,50 +156,22 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
             a_wi[i] = wo * a.stride - a.pad;
         }
     }
+    bool b_ok[BR];
+    size_t b_off[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+        const int row = rbase + i * RSTEP, n = n0 + row;
+        b_ok[i] = row < BN && n < a.cout_p;
+        b_off[i] = ((size_t)(b_ok[i] ? n : 0) * a.k_pad + sc * SEG) * ES;
+    }
 
     const int nkt = a.k_pad / BKE;
     const int kt0 = blockIdx.z * a.ktiles_per_split;
     const int kt1 = min(nkt, kt0 + a.ktiles_per_split);
     const int RS = a.R * a.S;
+    const u32x4 zero4 = {0u, 0u, 0u, 0u};
 
-    uint4 ra[AR], rb[BR];
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
-
-    auto gload = [&](int kt) {
-        const int k0 = kt * BKE + sc * SEG;
-        const int tap = k0 / a.cin_p;
-        const int c0 = k0 - tap * a.cin_p;
-        const int r = tap / a.S, s = tap - (tap / a.S) * a.S;
-        const bool kv = tap < RS;
-#pragma unroll
-        for (int i = 0; i < AR; ++i) {
-            const int hi = a_hi[i] + r, wi = a_wi[i] + s;
-            const bool ok = kv && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
-            const int hh = ok ? hi : 0, ww = ok ? wi : 0;  // no address arithmetic on rejected taps
-            const size_t off = ((size_t)(a_pix[i] + hh * a.W + ww) * a.cin_p + c0) * ES;
-            ra[i] = ok ? *(const uint4 *)((const char *)a.x + off) : zero4;
-        }
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            const int row = rbase + i * RSTEP, n = n0 + row;
-            const bool ok = row < BN && n < a.cout_p;
-            const size_t off = ((size_t)n * a.k_pad + (size_t)kt * BKE + sc * SEG) * ES;
-            rb[i] = ok ? *(const uint4 *)((const char *)a.w + off) : zero4;
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < AR; ++i) {
-            const int row = rbase + i * RSTEP;
-            sA[buf][row * 8 + (sc ^ (row & 7))] = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            const int row = rbase + i * RSTEP;
-            if (row < BN) sB[buf][row * 8 + (sc ^ (row & 7))] = rb[i];
-        }
-    };
-
+    u32x4 ra[AR], rb[BR];
     f4 acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -193,17 +179,52 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
         for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int lrow = lane & 15, lgrp = lane >> 4;
+
+// Issue the global loads of K-tile KT into ra / rb (no wait).
+#define DN_GLOAD(KT)                                                                           \
+    do {                                                                                       \
+        const int k0_ = (KT) * BKE + sc * SEG;                                                 \
+        const int tap_ = k0_ / a.cin_p;                                                        \
+        const int c0_ = k0_ - tap_ * a.cin_p;                                                  \
+        const int r_ = tap_ / a.S, s_ = tap_ - (tap_ / a.S) * a.S;                             \
+        const bool kv_ = tap_ < RS;                                                            \
+        _Pragma("unroll") for (int i = 0; i < AR; ++i) {                                       \
+            const int hi_ = a_hi[i] + r_, wi_ = a_wi[i] + s_;                                  \
+            const bool ok_ = kv_ && (unsigned)hi_ < (unsigned)a.H && (unsigned)wi_ < (unsigned)a.W; \
+            const int hh_ = ok_ ? hi_ : 0, ww_ = ok_ ? wi_ : 0;                                \
+            const size_t off_ = ((size_t)(a_pix[i] + hh_ * a.W + ww_) * a.cin_p + c0_) * ES;   \
+            ra[i] = ok_ ? gload16(a.x, off_) : zero4;                                          \
+        }                                                                                      \
+        const size_t kb_ = (size_t)(KT) * BKE * ES;                                            \
+        _Pragma("unroll") for (int i = 0; i < BR; ++i)                                         \
+            rb[i] = b_ok[i] ? gload16(a.w, b_off[i] + kb_) : zero4;                            \
+    } while (0)
+
+// Write ra / rb into LDS stage BUF (rows swizzled: segment s of row r sits at s ^ (r & 7)).
+#define DN_SSTORE(BUF)                                                                         \
+    do {                                                                                       \
+        _Pragma("unroll") for (int i = 0; i < AR; ++i) {                                       \
+            const int row_ = rbase + i * RSTEP;                                                \
+            sA[BUF][row_ * 8 + (sc ^ (row_ & 7))] = ra[i];                                     \
+        }                                                                                      \
+        _Pragma("unroll") for (int i = 0; i < BR; ++i) {                                       \
+            const int row_ = rbase + i * RSTEP;                                                \
+            if (row_ < BN) sB[BUF][row_ * 8 + (sc ^ (row_ & 7))] = rb[i];                      \
+        }                                                                                      \
+    } while (0)
+
     if (kt0 < kt1) {
-        gload(kt0);
-        sstore(0);
+        DN_GLOAD(kt0);
+        DN_SSTORE(0);
     }
     __syncthreads();
     for (int kt = kt0; kt < kt1; ++kt) {
         const int buf = (kt - kt0) & 1;
-        if (kt + 1 < kt1) gload(kt + 1);
+        const bool more = kt + 1 < kt1;
+        if (more) DN_GLOAD(kt + 1);
 #pragma unroll
         for (int ks = 0; ks < KSPT; ++ks) {
-            uint4 af[FM][SPL], bfr[FN][SPL];
+            u32x4 af[FM][SPL], bfr[FN][SPL];
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm) {
                 const int row = wm * WTM + fm * 16 + lrow;
@@ -227,9 +248,14 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn) mma<DT>(acc[fm][fn], af[fm], bfr[fn]);
         }
-        if (kt + 1 < kt1) sstore(buf ^ 1);
+        // keep the LDS stores of the next tile behind this tile's MFMAs, so the
+        // wait for its global loads overlaps the matrix work
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) DN_SSTORE(buf ^ 1);
         __syncthreads();
     }
+#undef DN_GLOAD
+#undef DN_SSTORE
 
     // ---- epilogue.  MFMA 16x16 output layout: lane holds column (lane & 15)
     // and rows 4*(lane >> 4) + i, i = 0..3.
@@ -310,6 +336,170 @@ __global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
     }
 }
 
+// ---------------------------------------------------------------- first layer
+// The network's first convolution reads the caller's NCHW FP32 image itself
+// (the ingest is fused): a 16 x 64 output tile stages its input window in LDS
+// as FP32 (FP8: pre-divided by the input scale), every lane gathers its MFMA
+// A-fragment taps from there, and the whole Cin*R*S (<= 32, FP8 <= 128) fits
+// one K block, so B (the packed weights, compact order k = (c*R + r)*S + s)
+// stays in registers for the whole tile.  With POOL, each 16-row MFMA block
+// is four 2x2 windows, so one lane's four accumulator rows are one window.
+
+constexpr int FT_H = 16, FT_W = 64;   // conv outputs per workgroup tile
+
+template <int DT, bool POOL>
+__global__ void __launch_bounds__(256) conv_first(FirstArgs a)
+{
+    constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
+    constexpr int KPL = (DT == F32) ? 4 : (DT == BF16 ? 8 : 32);  // K values per lane per K-step
+    constexpr int MAXNB = 4;                                      // up to 64 output channels
+    extern __shared__ float lds[];
+    const int LH = (FT_H - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = blockIdx.z;
+    const int th0 = blockIdx.y * FT_H, tw0 = blockIdx.x * FT_W;
+    const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
+
+    // ---- stage the input window (zero outside the image)
+    const int tot = a.C * LH * LW;
+    for (int e = tid; e < tot; e += 256) {
+        const int lc = e % LW, t = e / LW, lr = t % LH, c = t / LH;
+        const int hi = hi0 + lr, wi = wi0 + lc;
+        float v = 0.0f;
+        if ((unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W)
+            v = a.x[(((size_t)n * a.C + c) * a.H + hi) * a.W + wi] * a.in_inv_scale;
+        lds[e] = v;
+    }
+
+    // ---- this lane's K subset: LDS offsets of its taps (-1 = zero padding)
+    const int lrow = lane & 15, lgrp = lane >> 4;
+    const int K = a.C * a.R * a.S;
+    int toff[KSPT][KPL];
+#pragma unroll
+    for (int ks = 0; ks < KSPT; ++ks)
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) {
+            const int k = ks * 4 * KPL + lgrp * KPL + e;
+            int o = -1;
+            if (k < K) {
+                const int c = k / (a.R * a.S), rs = k - c * a.R * a.S, r = rs / a.S, sx = rs - r * a.S;
+                o = (c * LH + r) * LW + sx;
+            }
+            toff[ks][e] = o;
+        }
+    // ---- B fragments for every 16-channel block, kept in registers
+    const int nb_count = (a.cout_p + 15) / 16;
+    u32x4 bw[MAXNB][KSPT][SPL];
+#pragma unroll
+    for (int nb = 0; nb < MAXNB; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KSPT; ++ks)
+#pragma unroll
+            for (int j = 0; j < SPL; ++j) {
+                bw[nb][ks][j] = u32x4{0u, 0u, 0u, 0u};
+                if (nb < nb_count && nb * 16 + lrow < a.cout_p) {
+                    const size_t off = ((size_t)(nb * 16 + lrow) * a.k_pad + ks * 4 * KPL + lgrp * KPL) * esize(DT) + j * 16;
+                    bw[nb][ks][j] = gload16(a.w, off);
+                }
+            }
+    __syncthreads();
+
+    constexpr int BLOCKS = FT_H * FT_W / 16;  // 16-pixel MFMA blocks per tile
+    for (int b = wave; b < BLOCKS; b += 4) {
+        // this lane's pixel (A row) in the tile
+        int ho_l, wo_l;
+        if (POOL) {
+            const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
+            const int q = lrow, j = q >> 2;
+            ho_l = 2 * rp + ((q >> 1) & 1);
+            wo_l = 2 * (wg * 4 + j) + (q & 1);
+        } else {
+            ho_l = b / (FT_W / 16);
+            wo_l = (b % (FT_W / 16)) * 16 + lrow;
+        }
+        const int pbase = ho_l * a.stride * LW + wo_l * a.stride;
+        u32x4 af[KSPT][SPL];
+#pragma unroll
+        for (int ks = 0; ks < KSPT; ++ks) {
+            float v[KPL];
+#pragma unroll
+            for (int e = 0; e < KPL; ++e) v[e] = toff[ks][e] >= 0 ? lds[pbase + toff[ks][e]] : 0.0f;
+            if constexpr (DT == F32) {
+                af[ks][0] = u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3])};
+            } else if constexpr (DT == BF16) {
+                unsigned w4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w4[i] = (unsigned)f2bf(v[2 * i]) | ((unsigned)f2bf(v[2 * i + 1]) << 16);
+                af[ks][0] = u32x4{w4[0], w4[1], w4[2], w4[3]};
+            } else {
+                unsigned w8[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    w8[i] = (unsigned)f2e4m3(v[4 * i]) | ((unsigned)f2e4m3(v[4 * i + 1]) << 8) |
+                            ((unsigned)f2e4m3(v[4 * i + 2]) << 16) | ((unsigned)f2e4m3(v[4 * i + 3]) << 24);
+                af[ks][0] = u32x4{w8[0], w8[1], w8[2], w8[3]};
+                af[ks][1] = u32x4{w8[4], w8[5], w8[6], w8[7]};
+            }
+        }
+#pragma unroll
+        for (int nb = 0; nb < MAXNB; ++nb) {
+            if (nb >= nb_count) break;
+            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KSPT; ++ks) mma<DT>(acc, af[ks], bw[nb][ks]);
+            const int col = nb * 16 + lrow;
+            if (col >= a.cout_p) continue;
+            const float bias = a.bias[col];
+            const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl + bias, a.act, a.slope);
+            if (POOL) {
+                const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
+                const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
+                if (hp < (a.Ho >> 1) && wp < (a.Wo >> 1)) {
+                    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+                    store_el<DT>(a.y, (((size_t)n * (a.Ho >> 1) + hp) * (a.Wo >> 1) + wp) * a.cout_p + col, mx * a.out_inv_scale);
+                }
+            } else {
+                const int ho = th0 + ho_l;
+                if (ho < a.Ho) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int wo = tw0 + (b % (FT_W / 16)) * 16 + 4 * lgrp + i;
+                        if (wo < a.Wo)
+                            store_el<DT>(a.y, (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + col, v[i] * a.out_inv_scale);
+                    }
+                }
+            }
+        }
+    }
+}
+
+size_t first_lds_bytes(const FirstArgs &a)
+{
+    return (size_t)a.C * ((FT_H - 1) * a.stride + a.R) * ((FT_W - 1) * a.stride + a.S) * sizeof(float);
+}
+
+hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
+{
+    dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + FT_H - 1) / FT_H, a.batch);
+    const size_t lds = first_lds_bytes(a);
+#define DN_FIRST(D)                                                                                  \
+    do {                                                                                             \
+        if (a.pool) hipLaunchKernelGGL((conv_first<D, true>), grid, dim3(256), lds, s, a);           \
+        else hipLaunchKernelGGL((conv_first<D, false>), grid, dim3(256), lds, s, a);                 \
+    } while (0)
+    switch (dt) {
+    case F32: DN_FIRST(F32); break;
+    case BF16: DN_FIRST(BF16); break;
+    case FP8: DN_FIRST(FP8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DN_FIRST
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- dispatch
 
 static const TileCfg kTiles[] = {
@@ -323,6 +513,9 @@ static const TileCfg kTiles[] = {
     {256, 32, 4, 1},   // 7
     {64, 128, 1, 4},   // 8
     {64, 32, 2, 2},    // 9
+    {256, 256, 2, 2},  // 10: 4 waves of 128x128
+    {192, 256, 1, 4},  // 11: 57 M-tiles x 4 for M = 64*169
+    {128, 256, 1, 4},  // 12
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -351,6 +544,9 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 7: return go<DT, 256, 32, 4, 1>(a, s);
     case 8: return go<DT, 64, 128, 1, 4>(a, s);
     case 9: return go<DT, 64, 32, 2, 2>(a, s);
+    case 10: return go<DT, 256, 256, 2, 2>(a, s);
+    case 11: return go<DT, 192, 256, 1, 4>(a, s);
+    case 12: return go<DT, 128, 256, 1, 4>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

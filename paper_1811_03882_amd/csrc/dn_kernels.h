@@ -44,6 +44,26 @@ struct ConvArgs {
     int splits, ktiles_per_split;
 };
 
+// First convolution of a network, reading the NCHW FP32 input directly.
+// Weights packed in the compact order k = (c*R + r)*S + s, k_pad = first_kb().
+struct FirstArgs {
+    const float *x;        // NCHW FP32 image batch
+    const void *w;
+    const float *bias, *wscale;
+    void *y;               // NHWC output (pooled when pool = 1)
+    int batch, C, H, W, Ho, Wo, cout_p, k_pad;
+    int R, S, stride, pad;
+    int pool, act;
+    float slope;
+    float in_inv_scale;    // FP8: 1 / input scale (else 1)
+    float in_scale, out_inv_scale;
+};
+// K block of the first-layer kernel; a conv qualifies when C*R*S <= first_kb.
+__host__ __device__ constexpr int first_kb(int dt) { return dt == FP8 ? 128 : 32; }
+constexpr int FIRST_MAX_COUT = 64;
+hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s);
+size_t first_lds_bytes(const FirstArgs &a);
+
 struct TileCfg { int bm, bn, wm, wn; };
 
 int tile_count();
@@ -53,7 +73,8 @@ TileCfg tile_cfg(int i);
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
 
-hipError_t launch_fold_pack(int dt, const double *w, const double *bias, const double *mean,
+// compact = 1 packs k = (c*R + r)*S + s (first-layer kernel), else k = (r*S + s)*cin_p + c.
+hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta,
                             double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,
                             int k_pad, int cout_p, void *wout, float *bout, float *sout,

@@ -84,6 +84,7 @@ struct Op {
     int conv = -1;       // conv layer index (OP_CONV)
     int in = 0, in2 = -1, out = 0;  // value ids: value v = output of layer v-1, value 0 = net input
     bool pool = false, res = false;
+    bool first = false;  // first-layer kernel reading the NCHW FP32 input directly
     int H = 0, W = 0, Ho = 0, Wo = 0, cin_p = 0, cout = 0, cout_p = 0;  // op geometry
     int c_log = 0;       // logical channels of the output
     int tile = -1, splits = 1;
@@ -129,7 +130,20 @@ struct dn_net {
 
 // ---------------------------------------------------------------- helpers
 
+
 static int out_side_conv(int x, int k, int st, int pad) { return (x + 2 * pad - k) / st + 1; }
+
+// The network's first conv takes the fused-ingest kernel when its whole
+// receptive field fits one K block and its output channels fit in registers.
+static bool first_ok(int in_c, const dn_layer_desc &d, int dt)
+{
+    return d.kind == DN_CONV && in_c * d.ksize * d.ksize <= first_kb(dt) && d.cout <= FIRST_MAX_COUT &&
+           d.stride <= 2 && d.ksize <= 7;
+}
+static bool first_eligible(const dn_net *net, int dt)
+{
+    return !net->L.empty() && first_ok(net->o.in_c, net->L[0], dt);
+}
 static int out_side_pool(int x, int st) { return (x - 1) / st + 1; }
 
 extern "C" int dn_channel_pad(int dtype, int c)
@@ -268,6 +282,7 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         if (d.kind == DN_CONV) {
             op.kind = OP_CONV;
             op.conv = i;
+            op.first = (i == 0) && first_eligible(net, dtype);
             op.H = p.vals[i].h; op.W = p.vals[i].w; op.cin_p = p.vals[i].cp;
             op.Ho = p.vals[i + 1].h; op.Wo = p.vals[i + 1].w;
             op.cout = d.cout; op.cout_p = p.vals[i + 1].cp;
@@ -296,6 +311,8 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         }
         p.ops.push_back(op);
     }
+    // the first-layer kernel reads the caller's input itself: value 0 needs no buffer
+    if (!p.ops.empty() && p.ops[0].first) p.vals[0].bytes = 0;
     // liveness: value produced at op index (value 0 at -1), last use = max consumer op index
     p.vals[0].first = -1;
     for (int k = 0; k < (int)p.ops.size(); ++k) {
@@ -341,7 +358,7 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
     // split-K scratch and tile choice
     size_t ws = 0;
     for (Op &op : p.ops) {
-        if (op.kind != OP_CONV) continue;
+        if (op.kind != OP_CONV || op.first) continue;
         const dn_layer_desc &d = net->L[op.conv];
         const int K = d.ksize * d.ksize * op.cin_p;
         const int k_pad = (K + bk_el(dtype) - 1) / bk_el(dtype) * bk_el(dtype);
@@ -374,9 +391,43 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
 
 // ---------------------------------------------------------------- enqueue
 
-static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char *base, hipStream_t s, bool use32,
-                            int tile_override = -1, int splits_override = 0)
+static dn_status enqueue_first(const dn_net *net, const Plan &p, const Op &op, const float *x, char *base,
+                               hipStream_t s, bool use32)
 {
+    const dn_layer_desc &d = net->L[op.conv];
+    const ConvWeights &cw = net->cw[op.conv];
+    FirstArgs a{};
+    a.x = x;
+    a.w = use32 ? cw.w32 : cw.w;
+    a.bias = use32 ? cw.bias32 : cw.bias;
+    a.wscale = use32 ? cw.wscale32 : cw.wscale;
+    a.y = base + p.vals[op.out].off;
+    a.batch = p.batch; a.C = p.vals[0].c; a.H = p.h; a.W = p.w;
+    a.Ho = op.pool ? op.Ho * 2 : op.Ho;
+    a.Wo = op.pool ? op.Wo * 2 : op.Wo;
+    a.cout_p = op.cout_p;
+    a.k_pad = first_kb(use32 ? (int)F32 : p.dtype);
+    a.R = a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
+    a.pool = op.pool ? 1 : 0;
+    a.act = d.activation;
+    a.slope = net->o.leaky_slope;
+    a.in_inv_scale = a.in_scale = a.out_inv_scale = 1.0f;
+    if (!use32 && p.dtype == FP8) {
+        a.in_inv_scale = 1.0f / net->scale[0];
+        a.in_scale = net->scale[0];
+        a.out_inv_scale = 1.0f / net->scale[op.out];
+    }
+    HIPCHK(launch_conv_first(use32 ? (int)F32 : p.dtype, a, s));
+    return DN_OK;
+}
+
+static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char *base, hipStream_t s, bool use32,
+                            int tile_override = -1, int splits_override = 0, const float *xin = nullptr)
+{
+    if (op.kind == OP_CONV && op.first) {
+        if (!xin) return fail(DN_EINVAL, "first-layer kernel needs the input image");
+        return enqueue_first(net, p, op, xin, base, s, use32);
+    }
     if (op.kind == OP_CONV) {
         Op o2 = op;
         if (tile_override >= 0) o2.tile = tile_override;
@@ -406,8 +457,9 @@ static dn_status enqueue_resident(const dn_net *net, const Plan &p, char *base, 
 {
     const Value &v0 = p.vals[0];
     const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
-    HIPCHK(launch_ingest(p.dtype, x, p.batch, v0.c, v0.h, v0.w, v0.cp, in_inv, base + v0.off, s));
-    for (const Op &op : p.ops) STCHK(enqueue_op(net, p, op, base, s, false));
+    if (!p.ops[0].first)
+        HIPCHK(launch_ingest(p.dtype, x, p.batch, v0.c, v0.h, v0.w, v0.cp, in_inv, base + v0.off, s));
+    for (const Op &op : p.ops) STCHK(enqueue_op(net, p, op, base, s, false, -1, 0, x));
     const Value &vo = p.vals[p.out_val];
     const float osc = p.dtype == FP8 ? net->scale[p.out_val] : 1.0f;
     HIPCHK(launch_egress(p.dtype, base + vo.off, p.batch, vo.c, vo.h, vo.w, vo.cp, osc, y, s));
@@ -567,15 +619,16 @@ static dn_status pack_to(dn_net *net, int layer, int dt, const double *dw, const
     ConvWeights &cw = net->cw[layer];
     const dn_layer_desc &d = net->L[layer];
     const int cin_p = cpad(dt, cw.cin);
+    const bool compact = layer == 0 && first_eligible(net, dt);
     const int K = d.ksize * d.ksize * cin_p;
-    const int k_pad = (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const int k_pad = compact ? first_kb(dt) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
     const int cout_p = cpad(dt, d.cout);
     const size_t wb = (size_t)cout_p * k_pad * esize(dt);
     HIPCHK(hipMalloc(w, wb));
     HIPCHK(hipMalloc((void **)b, cout_p * sizeof(float)));
     HIPCHK(hipMalloc((void **)s, cout_p * sizeof(float)));
-    HIPCHK(launch_fold_pack(dt, dw, db, dm, dv, dg, dbe, net->o.bn_eps, has_bn, d.cout, cw.cin, d.ksize, d.ksize,
-                            cin_p, k_pad, cout_p, *w, *b, *s, st));
+    HIPCHK(launch_fold_pack(dt, compact ? 1 : 0, dw, db, dm, dv, dg, dbe, net->o.bn_eps, has_bn, d.cout, cw.cin,
+                            d.ksize, d.ksize, cin_p, k_pad, cout_p, *w, *b, *s, st));
     if (w == &cw.w) {
         cw.cin_p = cin_p; cw.cout = d.cout; cw.cout_p = cout_p; cw.k_pad = k_pad; cw.wbytes = wb;
     } else {
@@ -719,13 +772,19 @@ static dn_status forward_per_layer(dn_net *net, const void *x, int batch, int h,
     const Value &v0 = p.vals[0];
     const size_t xbytes = (size_t)batch * v0.c * h * w * 4;
     // input: host -> device, ingest, device -> host
-    HIPCHK(hipMemcpyAsync(base + p.xin_off, x, xbytes, hipMemcpyHostToDevice, s));
-    const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
-    HIPCHK(launch_ingest(p.dtype, (const float *)(base + p.xin_off), batch, v0.c, h, w, v0.cp, in_inv, base + v0.off, s));
-    HIPCHK(hipMemcpyAsync((*hv)[0], base + v0.off, v0.bytes, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    const float *xdev = (const float *)(base + p.xin_off);
+    if (!p.ops[0].first) {
+        HIPCHK(hipMemcpyAsync(base + p.xin_off, x, xbytes, hipMemcpyHostToDevice, s));
+        const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
+        HIPCHK(launch_ingest(p.dtype, xdev, batch, v0.c, h, w, v0.cp, in_inv, base + v0.off, s));
+        HIPCHK(hipMemcpyAsync((*hv)[0], base + v0.off, v0.bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     for (const Op &op : p.ops) {
-        HIPCHK(hipMemcpyAsync(base + p.vals[op.in].off, (*hv)[op.in], p.vals[op.in].bytes, hipMemcpyHostToDevice, s));
+        if (op.first)
+            HIPCHK(hipMemcpyAsync(base + p.xin_off, x, xbytes, hipMemcpyHostToDevice, s));
+        else
+            HIPCHK(hipMemcpyAsync(base + p.vals[op.in].off, (*hv)[op.in], p.vals[op.in].bytes, hipMemcpyHostToDevice, s));
         if (op.in2 >= 0)
             HIPCHK(hipMemcpyAsync(base + p.vals[op.in2].off, (*hv)[op.in2], p.vals[op.in2].bytes, hipMemcpyHostToDevice, s));
         if (op.kind == OP_CONV) {
@@ -736,7 +795,7 @@ static dn_status forward_per_layer(dn_net *net, const void *x, int batch, int h,
             HIPCHK(hipMemcpyAsync(cw.bias, hp + cw.wbytes, vb, hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(cw.wscale, hp + cw.wbytes + vb, vb, hipMemcpyHostToDevice, s));
         }
-        STCHK(enqueue_op(net, p, op, base, s, false));
+        STCHK(enqueue_op(net, p, op, base, s, false, -1, 0, xdev));
         HIPCHK(hipMemcpyAsync((*hv)[op.out], base + p.vals[op.out].off, p.vals[op.out].bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -787,10 +846,10 @@ extern "C" dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h,
     auto run = [&]() -> dn_status {
         HIPCHK(launch_zero_f32(amax, nv, s));
         const Value &v0 = p.vals[0];
-        HIPCHK(launch_ingest(F32, x, batch, v0.c, h, w, v0.cp, 1.0f, base + v0.off, s));
-        HIPCHK(launch_amax((const float *)(base + v0.off), (size_t)batch * h * w * v0.cp, amax, s));
+        if (!p.ops[0].first) HIPCHK(launch_ingest(F32, x, batch, v0.c, h, w, v0.cp, 1.0f, base + v0.off, s));
+        HIPCHK(launch_amax(x, (size_t)batch * v0.c * h * w, amax, s));
         for (const Op &op : p.ops) {
-            STCHK(enqueue_op(net, p, op, base, s, true));
+            STCHK(enqueue_op(net, p, op, base, s, true, -1, 0, x));
             const Value &vo = p.vals[op.out];
             HIPCHK(launch_amax((const float *)(base + vo.off), (size_t)batch * vo.h * vo.w * vo.cp, amax + op.out, s));
         }
@@ -866,7 +925,7 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
     char *base = (char *)net->arena;
     dn_status rc = DN_OK;
     for (const Op &op : p.ops) {
-        if (op.kind != OP_CONV) continue;
+        if (op.kind != OP_CONV || op.first) continue;
         const dn_layer_desc &d = net->L[op.conv];
         const std::string sig = conv_sig(p.dtype, op, batch, d.ksize, d.stride);
         if (net->tuned.count(sig)) continue;
@@ -920,7 +979,7 @@ extern "C" dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int 
     STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
     for (const Op &op : p.ops) {
         if (op.kind == OP_CONV && op.conv == layer) {
-            if (tile) *tile = op.tile;
+            if (tile) *tile = op.first ? -2 : op.tile;
             if (splits) *splits = op.splits;
             if (fused_pool) *fused_pool = op.pool;
             if (fused_res) *fused_res = op.res;
@@ -945,12 +1004,21 @@ extern "C" dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int
         if (op.layer == layer || op.conv == layer) found = &op;
     if (!found) return fail(DN_EINVAL, "no op computes layer %d", layer);
     hipStream_t s = (hipStream_t)stream;
+    float *xin = nullptr;
+    if (found->first) {  // the first-layer kernel reads an NCHW image: time it on zeros
+        const size_t xb = (size_t)batch * net->o.in_c * h * w * sizeof(float);
+        HIPCHK(hipMalloc(&xin, xb));
+        if (hipMemsetAsync(xin, 0, xb, s) != hipSuccess) {
+            (void)hipFree(xin);
+            return fail(DN_EHIP, "memset");
+        }
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     dn_status rc = DN_OK;
     if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event record");
-    for (int i = 0; i < iters && rc == DN_OK; ++i) rc = enqueue_op(net, p, *found, (char *)net->arena, s, false);
+    for (int i = 0; i < iters && rc == DN_OK; ++i) rc = enqueue_op(net, p, *found, (char *)net->arena, s, false, -1, 0, xin);
     if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
         rc = fail(DN_EHIP, "timed launches failed");
     float ms = 0.f;
@@ -958,6 +1026,10 @@ extern "C" dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int
     *avg_ms = ms / iters;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (xin) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(xin);
+    }
     return rc;
 }
 
@@ -976,12 +1048,19 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     if (d->pool && d->residual) return fail(DN_EUNSUPPORTED, "conv desc: pool and residual together");
     const int dt = d->dtype;
     const int cin_p = cpad(dt, d->in_c), cout_p = cpad(dt, d->cout);
+    if (d->input_nchw) {
+        dn_layer_desc ld{DN_CONV, d->cout, d->ksize, d->stride, d->pad, 0, d->activation, 0};
+        if (!first_ok(d->in_c, ld, dt))
+            return fail(DN_EUNSUPPORTED, "conv desc: input_nchw needs in_c*k*k <= %d, cout <= %d, stride <= 2",
+                        first_kb(dt), FIRST_MAX_COUT);
+        if (d->residual) return fail(DN_EUNSUPPORTED, "conv desc: input_nchw with residual");
+    }
     const int Ho = out_side_conv(d->in_h, d->ksize, d->stride, d->pad);
     const int Wo = out_side_conv(d->in_w, d->ksize, d->stride, d->pad);
     if (Ho <= 0 || Wo <= 0) return fail(DN_EINVAL, "conv desc: output is empty");
     if (d->pool && (Ho % 2 || Wo % 2)) return fail(DN_EUNSUPPORTED, "conv desc: fused pool needs an even output (%dx%d)", Ho, Wo);
     const int K = d->ksize * d->ksize * cin_p;
-    const int k_pad = (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const int k_pad = d->input_nchw ? first_kb(dt) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
     const long Ml = (long)d->batch * Ho * Wo;
     if (Ml > (1L << 30)) return fail(DN_EUNSUPPORTED, "conv desc: too many output pixels");
     const int M = (int)Ml;
@@ -991,8 +1070,9 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     if (t < 0) t = ht;
     if (sp <= 0) sp = (d->tile < 0) ? hs : 1;
     if (t >= tile_count()) return fail(DN_EINVAL, "tile %d out of range", t);
-    const int nkt = k_pad / bk_el(dt);
+    const int nkt = std::max(1, k_pad / bk_el(dt));
     if (sp > nkt) sp = nkt;
+    if (d->input_nchw) sp = 1;
     if (a) {
         memset(a, 0, sizeof *a);
         a->batch = d->batch; a->H = d->in_h; a->W = d->in_w; a->cin_p = cin_p;
@@ -1046,7 +1126,7 @@ extern "C" dn_status dn_conv_pack(const dn_conv_desc *d, const double *w, const 
     bool ok = cp(dw, w, nw) && cp(db, bias, nv);
     if (ok && all_bn) ok = cp(dm, mean, nv) && cp(dv, var, nv) && cp(dg, gamma, nv) && cp(dbe, beta, nv);
     if (!ok) rc = fail(DN_EHIP, "conv pack upload failed");
-    if (rc == DN_OK && launch_fold_pack(dt, dw, db, dm, dv, dg, dbe, eps, all_bn ? 1 : 0, d->cout, d->in_c, d->ksize,
+    if (rc == DN_OK && launch_fold_pack(dt, d->input_nchw ? 1 : 0, dw, db, dm, dv, dg, dbe, eps, all_bn ? 1 : 0, d->cout, d->in_c, d->ksize,
                                         d->ksize, cin_p, k_pad, cout_p, w_packed, bias_out, wscale_out, s) != hipSuccess)
         rc = fail(DN_EHIP, "fold/pack launch failed");
     if (hipStreamSynchronize(s) != hipSuccess && rc == DN_OK) rc = fail(DN_EHIP, "fold/pack failed");
@@ -1067,6 +1147,18 @@ extern "C" dn_status dn_conv2d(const dn_conv_desc *d, const void *x, const void 
     if (d->residual && !res) return fail(DN_EINVAL, "conv2d: residual requested without res");
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(DN_EINVAL, "conv2d: split-K %d needs %zu workspace bytes (%zu given)", splits, need, ws_bytes);
+    if (d->input_nchw) {
+        FirstArgs f{};
+        f.x = (const float *)x; f.w = w_packed; f.bias = bias; f.wscale = wscale; f.y = y;
+        f.batch = a.batch; f.C = d->in_c; f.H = a.H; f.W = a.W; f.Ho = a.Ho; f.Wo = a.Wo;
+        f.cout_p = a.cout_p; f.k_pad = a.k_pad; f.R = f.S = d->ksize; f.stride = d->stride; f.pad = d->pad;
+        f.pool = a.pool; f.act = a.act; f.slope = a.slope;
+        f.in_inv_scale = d->dtype == DN_FP8_E4M3 ? 1.0f / d->in_scale : 1.0f;
+        f.in_scale = a.in_scale;
+        f.out_inv_scale = a.out_inv_scale;
+        HIPCHK(launch_conv_first(d->dtype, f, (hipStream_t)stream));
+        return DN_OK;
+    }
     a.x = x; a.w = w_packed; a.bias = bias; a.wscale = wscale;
     a.res = d->residual ? res : nullptr;
     a.y = y;

@@ -49,7 +49,8 @@ class ConvDesc(ctypes.Structure):
                 ("stride", ctypes.c_int), ("pad", ctypes.c_int), ("activation", ctypes.c_int),
                 ("leaky_slope", ctypes.c_float), ("pool", ctypes.c_int), ("residual", ctypes.c_int),
                 ("dtype", ctypes.c_int), ("in_scale", ctypes.c_float), ("res_scale", ctypes.c_float),
-                ("out_scale", ctypes.c_float), ("tile", ctypes.c_int), ("splits", ctypes.c_int)]
+                ("out_scale", ctypes.c_float), ("tile", ctypes.c_int), ("splits", ctypes.c_int),
+                ("input_nchw", ctypes.c_int)]
 
 
 class PoolDesc(ctypes.Structure):
@@ -259,9 +260,9 @@ class Net:
 
 def conv_desc(batch, in_h, in_w, in_c, cout, ksize, stride, pad, activation=LEAKY, slope=0.1,
               pool=0, residual=0, dtype=F32, in_scale=1.0, res_scale=1.0, out_scale=1.0,
-              tile=-1, splits=0) -> ConvDesc:
+              tile=-1, splits=0, input_nchw=0) -> ConvDesc:
     return ConvDesc(batch, in_h, in_w, in_c, cout, ksize, stride, pad, activation, slope, pool,
-                    residual, dtype, in_scale, res_scale, out_scale, tile, splits)
+                    residual, dtype, in_scale, res_scale, out_scale, tile, splits, input_nchw)
 
 
 def conv_sizes(d: ConvDesc) -> Tuple[int, int, int]:

@@ -65,17 +65,18 @@ def from_storage(dn, dtype, buf, n, c, h, w, scale=1.0, stream=None):
 
 
 def run_conv(dn, dtype, x, p, ksize, stride, pad, act, slope=0.1, eps=1e-5, pool=0, res=None,
-             in_scale=1.0, res_scale=1.0, out_scale=1.0, tile=-1, splits=0):
-    """One conv layer through dn_conv_pack + dn_conv2d on FP64 NCHW inputs."""
+             in_scale=1.0, res_scale=1.0, out_scale=1.0, tile=-1, splits=0, input_nchw=0):
+    """One conv layer through dn_conv_pack + dn_conv2d on FP64 NCHW inputs
+    (input_nchw = 1: the first-layer kernel reading the FP32 NCHW image)."""
     torch = torch_cuda()
     n, c, h, w = x.shape
     cout = p.w.shape[0]
     d = dn.conv_desc(n, h, w, c, cout, ksize, stride, pad, act, slope, 2 if pool else 0, 1 if res is not None else 0,
-                     dtype, in_scale, res_scale, out_scale, tile, splits)
+                     dtype, in_scale, res_scale, out_scale, tile, splits, input_nchw)
     wb, vb, wsb = dn.conv_sizes(d)
     wbuf, bbuf, sbuf = empty_bytes(wb), empty_bytes(vb), empty_bytes(vb)
     dn.conv_pack(d, p.w, p.bias, p.mean, p.var, p.gamma, p.beta, eps, wbuf, bbuf, sbuf)
-    xb = to_storage(dn, dtype, x, in_scale)
+    xb = dev(x.astype(np.float32)) if input_nchw else to_storage(dn, dtype, x, in_scale)
     ho = (h + 2 * pad - ksize) // stride + 1
     wo = (w + 2 * pad - ksize) // stride + 1
     if pool:

@@ -1,0 +1,99 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dn.h, and the host-side validation paths report errors
+through dn_last_error()."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dn.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\**\s*\b(dn_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def dn():
+    from paper_1811_03882_amd import dn as _dn
+    return _dn
+
+
+def test_every_declared_symbol_is_exported(dn):
+    names = declared_functions()
+    assert len(names) >= 20, names
+    lib = ctypes.CDLL(dn.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding covers the whole ABI
+    assert set(names) <= set(dn.SIGNATURES), set(names) - set(dn.SIGNATURES)
+
+
+def test_channel_pad_and_tiles(dn):
+    assert dn.channel_pad(dn.F32, 3) == 4
+    assert dn.channel_pad(dn.BF16, 3) == 8
+    assert dn.channel_pad(dn.FP8, 125) == 128
+    assert dn.channel_pad(7, 3) == -1
+    assert dn.tile_count() >= 10
+    for t in range(dn.tile_count()):
+        bm, bn, wm, wn = dn.tile_info(t)
+        assert bm % (16 * wm) == 0 and bn % (16 * wn) == 0
+    with pytest.raises(dn.DnError) as e:
+        dn.tile_info(dn.tile_count())
+    assert e.value.status == dn.DN_EINVAL
+
+
+def test_conv_sizes_host_arithmetic(dn):
+    d = dn.conv_desc(64, 13, 13, 1024, 1024, 3, 1, 1, dtype=dn.BF16, tile=4, splits=1)
+    w, v, ws = dn.conv_sizes(d)
+    assert w == 1024 * 9 * 1024 * 2 and v == 1024 * 4 and ws == 0
+    d = dn.conv_desc(1, 13, 13, 1024, 1024, 3, 1, 1, dtype=dn.F32, tile=0, splits=4)
+    assert dn.conv_sizes(d)[2] == 4 * 169 * 1024 * 4
+    d = dn.conv_desc(1, 416, 416, 3, 16, 3, 1, 1, dtype=dn.BF16, pool=2, input_nchw=1)
+    assert dn.conv_sizes(d) == (16 * 32 * 2, 16 * 4, 0)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(pool=2, in_h=13, in_w=13), "DN_EUNSUPPORTED"),      # odd output with fused pool
+    (dict(pool=3), "DN_EUNSUPPORTED"),
+    (dict(batch=0), "DN_EINVAL"),
+    (dict(activation=7), "DN_EINVAL"),
+    (dict(dtype=9), "DN_EINVAL"),
+    (dict(input_nchw=1, in_c=64), "DN_EUNSUPPORTED"),         # receptive field > one K block
+    (dict(pool=2, residual=1), "DN_EUNSUPPORTED"),
+])
+def test_conv_desc_validation(dn, kw, status):
+    base = dict(batch=1, in_h=16, in_w=16, in_c=8, cout=8, ksize=3, stride=1, pad=1)
+    base.update(kw)
+    with pytest.raises(dn.DnError) as e:
+        dn.conv_sizes(dn.conv_desc(**base))
+    assert e.value.status == getattr(dn, status)
+    assert dn.last_error()
+
+
+def test_net_create_validation_without_gpu(dn):
+    import synth
+    bad = [synth.conv(16, 3), synth.shortcut(5)]
+    with pytest.raises(dn.DnError) as e:
+        dn.Net(bad, 3, 32, 32, 1)
+    assert e.value.status == dn.DN_EINVAL and "src" in dn.last_error()
+    with pytest.raises(dn.DnError) as e:
+        dn.Net([synth.conv(16, 3)], 0, 32, 32, 1)
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:
+        dn.Net([synth.conv(16, 3)], 3, 32, 32, 1, dtype=5)
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:
+        dn.Net([synth.Layer(9)], 3, 32, 32, 1)
+    assert e.value.status == dn.DN_EINVAL
+
+
+def test_null_safe_destroy(dn):
+    dn.LIB.dn_net_destroy(None)
+    st = dn.LIB.dn_forward(None, None, 1, 1, 1, None, None)
+    assert st == dn.DN_EINVAL

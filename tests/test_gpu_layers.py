@@ -108,6 +108,33 @@ def test_conv_layer_parity(dn, dtype, shape):
     assert err < G.GATE[dtype]
 
 
+# first-layer kernel (fused ingest): (batch, H, W, Cin, Cout, k, stride, pad, pool)
+FIRST = [
+    (2, 32, 32, 3, 16, 3, 1, 1, 1),     # single block / plain9 stem, pooled
+    (1, 40, 72, 3, 32, 3, 1, 1, 0),     # residual stem, ragged tile edges, 2 channel blocks
+    (1, 30, 34, 3, 12, 3, 2, 1, 0),     # stride 2, odd channel count
+    (2, 18, 20, 1, 48, 5, 1, 2, 1),     # 5x5, single input channel, 3 channel blocks
+]
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", FIRST, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8] + ("_pool" if s[8] else ""))
+def test_first_layer_kernel_parity(dn, dtype, shape):
+    b, h, w, cin, cout, k, st, pad, pool = shape
+    p = _params(cout, cin, k, 200 + cout)
+    x = synth.make_tensor((b, cin, h, w), 13, cout, 0.0, 1.0)
+    ref = _oracle_conv(x, p, k, st, pad, 1, pool)
+    kw = dict(in_scale=G.fp8_scale(x), out_scale=G.fp8_scale(ref)) if dtype == dn.FP8 else {}
+    got = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, input_nchw=1, **kw)
+    err = G.rel_l2(got, ref)
+    print("first-layer %s %s rel_l2=%.3e" % (G.NAME[dtype], shape, err))
+    assert err < G.GATE[dtype]
+    if dtype == dn.F32:
+        # same layer through the generic implicit-GEMM path: equal within FP32 rounding
+        gen = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool)
+        assert G.rel_l2(got, gen) < 1e-6
+
+
 @pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
 def test_every_tile_config_agrees(dn, dtype):
     b, h, w, cin, cout, k = 2, 12, 14, 40, 72, 3
