@@ -112,6 +112,60 @@ __device__ __forceinline__ u32x4 gload16(const void *base, size_t byte_off)
     return *(const GLOBAL u32x4 *)((const GLOBAL char *)base + byte_off);
 }
 
+// Epilogue shared by the implicit-GEMM kernels.  MFMA 16x16 output layout:
+// lane holds column (lane & 15) and rows 4*(lane >> 4) + i, i = 0..3; rowb /
+// colb are this lane's first row / column.  With split-K the raw FP32
+// partial sums go to the scratch plane of this split instead.
+template <int DT, int FM, int FN>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][FN], int rowb, int colb)
+{
+    if (a.splits > 1) {
+        float *P = a.partial + (size_t)blockIdx.z * a.M * a.cout_p;
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int col = colb + fn * 16;
+            if (col >= a.cout_p) continue;
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = rowb + fm * 16 + i;
+                    if (m < a.M) P[(size_t)m * a.cout_p + col] = acc[fm][fn][i];
+                }
+        }
+        return;
+    }
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+        const int col = colb + fn * 16;
+        if (col >= a.cout_p) continue;
+        const float bias = a.bias[col];
+        const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
+            const int mb = rowb + fm * 16;
+            if (mb >= a.M) continue;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = activate(acc[fm][fn][i] * scl + bias, a.act, a.slope);
+            if (a.pool) {
+                // rows mb..mb+3 are one 2x2 window (M is a multiple of 4 here)
+                const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+                store_el<DT>(a.y, (size_t)(mb >> 2) * a.cout_p + col, mx * a.out_inv_scale);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = mb + i;
+                    if (m >= a.M) break;
+                    float o = v[i];
+                    if (a.res) o += load_el<DT>(a.res, (size_t)m * a.cout_p + col) * a.res_scale;
+                    store_el<DT>(a.y, (size_t)m * a.cout_p + col, o * a.out_inv_scale);
+                }
+            }
+        }
+    }
+}
+
 template <int DT, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 {
@@ -257,55 +311,182 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 #undef DN_GLOAD
 #undef DN_SSTORE
 
-    // ---- epilogue.  MFMA 16x16 output layout: lane holds column (lane & 15)
-    // and rows 4*(lane >> 4) + i, i = 0..3.
-    const int colb = n0 + wn * WTN + lrow;
-    const int rowb = m0 + wm * WTM + 4 * lgrp;
-    if (a.splits > 1) {
-        float *P = a.partial + (size_t)blockIdx.z * a.M * a.cout_p;
+    conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
+}
+
+// ---------------------------------------------------------------- LDS-DMA variant
+// Same GEMM, but the K-tiles travel global -> LDS directly
+// (buffer_load_dwordx4 ... lds: lane L of a wave instruction writes bytes
+// [16L, 16L + 16) of a 1 KB LDS block, i.e. row L/8, physical segment L%8 of
+// an 8-row group).  No VGPR staging, so NS-1 K-tiles can be in flight while
+// one is multiplied.  Out-of-range taps and rows use an offset past the
+// buffer's size, for which the buffer load returns zeros.
+#define DN_OOB 0x80000000u
+
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+template <int N> __device__ __forceinline__ void wait_vm()
+{
+    // s_waitcnt vmcnt(N) with expcnt / lgkmcnt left at their maxima (no wait)
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer resource (V#) for raw 32-bit-offset loads: base, stride 0,
+// num_records = size in bytes (loads at or past it return zeros).
+__device__ __forceinline__ i32x4 make_rsrc(const void *base, unsigned bytes)
+{
+    const unsigned long long b = (unsigned long long)base;
+    return i32x4{(int)(unsigned)b, (int)(unsigned)(b >> 32), (int)bytes, 0x00020000};
+}
+
+// One 16-byte-per-lane global -> LDS transfer.  Issued as inline assembly so
+// that the compiler does not see an LDS write in flight: it would otherwise
+// drain every outstanding transfer (vmcnt(0)) before each LDS read, and the
+// pipeline below could not keep K-tiles in flight.  Completion is tracked by
+// the explicit vmcnt waits + barrier of the main loop.
+__device__ __forceinline__ void dma16(const i32x4 &rsrc, unsigned voff, const void *lds_dst)
+{
+    // the destination is wave-uniform by construction; say so to the compiler
+    const unsigned m0v = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(const __attribute__((address_space(3))) void *)lds_dst);
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :
+                 : "s"(m0v), "v"(voff), "s"(rsrc)
+                 : "memory", "m0");
+}
+
+template <int DT, int BM, int BN, int WM, int WN, int NS>
+__global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
+{
+    constexpr int NW = WM * WN, NT = 64 * NW;
+    constexpr int ES = esize(DT), SEG = seg_el(DT), BKE = bk_el(DT);
+    constexpr int RSTEP = NT / 8;
+    constexpr int AR = BM / RSTEP, BR = BN / RSTEP;     // transfers per wave per K-tile
+    constexpr int LPT = AR + BR;
+    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
+    static_assert(BM % RSTEP == 0 && BN % RSTEP == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
+    static_assert(NS >= 2 && NS <= 4 && LPT * (NS - 2) < 64, "pipeline depth");
+
+    __shared__ u32x4 sA[NS][BM * 8];
+    __shared__ u32x4 sB[NS][BN * 8];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int ntn = (a.cout_p + BN - 1) / BN;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int m0 = (logical / ntn) * BM, n0 = (logical % ntn) * BN;
+
+    // lane L of a transfer fills row L/8, physical segment L%8 of an 8-row
+    // group; with the row swizzle that is logical segment (L%8) ^ (L/8)
+    const int sc = (lane & 7) ^ ((lane >> 3) & 7);
+    const int rbase = tid >> 3;  // this lane's row in the wave's first group
+    int a_pix[AR], a_hi[AR], a_wi[AR];
 #pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-            const int col = colb + fn * 16;
-            if (col >= a.cout_p) continue;
+    for (int i = 0; i < AR; ++i) {
+        const int m = m0 + rbase + i * RSTEP;
+        a_pix[i] = 0; a_hi[i] = -(1 << 28); a_wi[i] = 0;
+        if (m < a.M) {
+            int n, ho, wo;
+            if (a.pool) {
+                const int q = m & 3, win = m >> 2, wp2 = a.Wo >> 1, hp2 = a.Ho >> 1;
+                const int wp = win % wp2, t = win / wp2;
+                ho = 2 * (t % hp2) + (q >> 1); wo = 2 * wp + (q & 1); n = t / hp2;
+            } else {
+                wo = m % a.Wo; const int t = m / a.Wo; ho = t % a.Ho; n = t / a.Ho;
+            }
+            a_pix[i] = n * a.H * a.W;
+            a_hi[i] = ho * a.stride - a.pad;
+            a_wi[i] = wo * a.stride - a.pad;
+        }
+    }
+    unsigned b_off[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+        const int n = n0 + rbase + i * RSTEP;
+        b_off[i] = n < a.cout_p ? (unsigned)(((size_t)n * a.k_pad + sc * SEG) * ES) : DN_OOB;
+    }
+    const i32x4 rx = make_rsrc(a.x, a.x_bytes);
+    const i32x4 rw = make_rsrc(a.w, a.w_bytes);
+
+    const int nkt = a.k_pad / BKE;
+    const int kt0 = blockIdx.z * a.ktiles_per_split;
+    const int kt1 = min(nkt, kt0 + a.ktiles_per_split);
+    const int RS = a.R * a.S;
+
+    auto issue = [&](int kt, int st) {
+        const int k0 = kt * BKE + sc * SEG;
+        const int tap = k0 / a.cin_p;
+        const int c0 = k0 - tap * a.cin_p;
+        const int r = tap / a.S, s = tap - (tap / a.S) * a.S;
+        const bool kv = tap < RS;
+#pragma unroll
+        for (int i = 0; i < AR; ++i) {
+            const int hi = a_hi[i] + r, wi = a_wi[i] + s;
+            const bool ok = kv && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+            const unsigned off = ok ? (unsigned)(((a_pix[i] + hi * a.W + wi) * a.cin_p + c0) * ES) : DN_OOB;
+            dma16(rx, off, &sA[st][(wave + i * NW) * 64]);
+        }
+        const unsigned kb = (unsigned)(kt * BKE * ES);
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            const unsigned off = b_off[i] == DN_OOB ? DN_OOB : b_off[i] + kb;
+            dma16(rw, off, &sB[st][(wave + i * NW) * 64]);
+        }
+    };
+
+    f4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int lrow = lane & 15, lgrp = lane >> 4;
+
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st)
+        if (kt0 + st < kt1) issue(kt0 + st, st);
+
+    int cs = 0;  // stage holding tile kt
+    for (int kt = kt0; kt < kt1; ++kt) {
+        // this wave's transfers of tile kt landed; later tiles may stay in flight
+        const int after = min(NS - 2, kt1 - 1 - kt);  // tiles issued after kt so far
+        if (after >= 2) wait_vm<LPT * 2>();
+        else if (after == 1) wait_vm<LPT>();
+        else wait_vm<0>();
+        lds_barrier();  // every wave's transfers landed; every wave is done with tile kt-1
+        if (kt + NS - 1 < kt1) issue(kt + NS - 1, cs == 0 ? NS - 1 : cs - 1);
+#pragma unroll
+        for (int ks = 0; ks < KSPT; ++ks) {
+            u32x4 af[FM][SPL], bfr[FN][SPL];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int row = wm * WTM + fm * 16 + lrow;
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const int seg = ks * 4 * SPL + lgrp * SPL + j;
+                    af[fm][j] = sA[cs][row * 8 + (seg ^ (row & 7))];
+                }
+            }
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                const int row = wn * WTN + fn * 16 + lrow;
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const int seg = ks * 4 * SPL + lgrp * SPL + j;
+                    bfr[fn][j] = sB[cs][row * 8 + (seg ^ (row & 7))];
+                }
+            }
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int m = rowb + fm * 16 + i;
-                    if (m < a.M) P[(size_t)m * a.cout_p + col] = acc[fm][fn][i];
-                }
+                for (int fn = 0; fn < FN; ++fn) mma<DT>(acc[fm][fn], af[fm], bfr[fn]);
         }
-        return;
+        cs = cs + 1 == NS ? 0 : cs + 1;
     }
-#pragma unroll
-    for (int fn = 0; fn < FN; ++fn) {
-        const int col = colb + fn * 16;
-        if (col >= a.cout_p) continue;
-        const float bias = a.bias[col];
-        const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
-#pragma unroll
-        for (int fm = 0; fm < FM; ++fm) {
-            const int mb = rowb + fm * 16;
-            if (mb >= a.M) continue;
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = activate(acc[fm][fn][i] * scl + bias, a.act, a.slope);
-            if (a.pool) {
-                // rows mb..mb+3 are one 2x2 window (M is a multiple of 4 here)
-                const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
-                store_el<DT>(a.y, (size_t)(mb >> 2) * a.cout_p + col, mx * a.out_inv_scale);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int m = mb + i;
-                    if (m >= a.M) break;
-                    float o = v[i];
-                    if (a.res) o += load_el<DT>(a.res, (size_t)m * a.cout_p + col) * a.res_scale;
-                    store_el<DT>(a.y, (size_t)m * a.cout_p + col, o * a.out_inv_scale);
-                }
-            }
-        }
-    }
+    conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
 }
 
 // Split-K finish: sum the partials in split order, then the same epilogue.
@@ -516,6 +697,13 @@ static const TileCfg kTiles[] = {
     {256, 256, 2, 2},  // 10: 4 waves of 128x128
     {192, 256, 1, 4},  // 11: 57 M-tiles x 4 for M = 64*169
     {128, 256, 1, 4},  // 12
+    // LDS-DMA pipeline variants (bm, bn, waves_m, waves_n; stages in dispatch)
+    {256, 128, 2, 2},  // 13: 3 stages
+    {128, 128, 2, 2},  // 14: 4 stages
+    {256, 256, 2, 4},  // 15: 2 stages
+    {192, 256, 1, 4},  // 16: 2 stages
+    {128, 256, 2, 4},  // 17: 3 stages
+    {256, 128, 2, 4},  // 18: 3 stages, 8 waves
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -527,6 +715,21 @@ static hipError_t go(const ConvArgs &a, hipStream_t s)
     const int mt = (a.M + BM - 1) / BM, nt = (a.cout_p + BN - 1) / BN;
     dim3 grid(mt * nt, 1, a.splits);
     hipLaunchKernelGGL((conv_igemm<DT, BM, BN, WM, WN>), grid, dim3(64 * WM * WN), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int DT, int BM, int BN, int WM, int WN, int NS>
+static hipError_t go_dl(ConvArgs a, hipStream_t s)
+{
+    // buffer offsets are 32-bit: the LDS-DMA kernels need tensors below 2 GiB
+    const size_t xb = (size_t)a.batch * a.H * a.W * a.cin_p * esize(DT);
+    const size_t wb = (size_t)a.cout_p * a.k_pad * esize(DT);
+    if (xb >= DN_OOB || wb >= DN_OOB) return go<DT, BM, BN, WM, WN>(a, s);
+    a.x_bytes = (unsigned)xb;
+    a.w_bytes = (unsigned)wb;
+    const int mt = (a.M + BM - 1) / BM, nt = (a.cout_p + BN - 1) / BN;
+    dim3 grid(mt * nt, 1, a.splits);
+    hipLaunchKernelGGL((conv_igemm_dl<DT, BM, BN, WM, WN, NS>), grid, dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
 
@@ -547,6 +750,12 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 10: return go<DT, 256, 256, 2, 2>(a, s);
     case 11: return go<DT, 192, 256, 1, 4>(a, s);
     case 12: return go<DT, 128, 256, 1, 4>(a, s);
+    case 13: return go_dl<DT, 256, 128, 2, 2, 3>(a, s);
+    case 14: return go_dl<DT, 128, 128, 2, 2, 4>(a, s);
+    case 15: return go_dl<DT, 256, 256, 2, 4, 2>(a, s);
+    case 16: return go_dl<DT, 192, 256, 1, 4, 2>(a, s);
+    case 17: return go_dl<DT, 128, 256, 2, 4, 3>(a, s);
+    case 18: return go_dl<DT, 256, 128, 2, 4, 3>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

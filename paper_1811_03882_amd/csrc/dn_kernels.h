@@ -42,6 +42,7 @@ struct ConvArgs {
     float slope;
     float in_scale, res_scale, out_inv_scale;  // FP8 scales (1 otherwise)
     int splits, ktiles_per_split;
+    unsigned x_bytes, w_bytes;  // buffer sizes (set by the launcher)
 };
 
 // First convolution of a network, reading the NCHW FP32 input directly.
