@@ -110,6 +110,43 @@ def cpu_baseline(budget_s: float = 12.0):
                       "OpenMP over (image, channel), %.1f s" % (n, dt)}
 
 
+def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print):
+    """Open-loop serving of the mixed-resolution trace: BF16 continuous batching
+    vs the FP32 plain path (batch 1, one stream, arrival order) on the same GPU."""
+    import synth
+    from paper_1811_03882_amd import serve
+    net = synth.plain9()
+    params = synth.make_params(net, synth.SEED_PLAIN)
+    trace = synth.serving_trace(n_requests, rate, synth.SEED_SERVING)
+    sizes = trace.sizes
+    pool = {s: [synth.serving_image(1000000 + 8 * j + k, s).astype(np.float32)[0] for k in range(8)]
+            for j, s in enumerate(sizes)}
+    image_of = lambda r: pool[r.size][r.rid % 8]
+    out = {}
+    for name, dtype, slots, max_batch, bucketed, graph in (("bf16_continuous_batching", dn.BF16, 8, 64, True, False),
+                                                          ("f32_plain_batch1", dn.F32, 1, 1, False, True)):
+        log("[bench] serving %s" % name)
+        n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=graph)
+        n.load_params(params)
+        budget = (32 << 30) if bucketed else (1 << 30)  # the HBM activation budget of the serving config
+        ex = serve.DnExecutor(n, torch, budget_bytes=budget, n_slots=slots, image_of=image_of,
+                              max_batch=max_batch, max_size=max(sizes), keep_outputs=False)
+        # warm-up: one request per size (graph capture / first launches), not counted
+        serve.Scheduler(ex, ex.pool.numel(), sizes, max_batch=max_batch, bucketed=bucketed,
+                        pad_pow2=bucketed).run([serve.Request(-1 - k, s, 0.0) for k, s in enumerate(sizes)])
+        torch.cuda.synchronize()
+        sch = serve.Scheduler(ex, ex.pool.numel(), sizes, max_batch=max_batch, bucketed=bucketed, pad_pow2=bucketed)
+        st = sch.run(serve.make_requests(trace))
+        d = st.as_dict()
+        d.update({"dtype": {0: "f32", 1: "bf16"}[dtype], "slots": slots, "budget_gb": ex.pool.numel() / 2 ** 30})
+        out[name] = d
+        log("[bench]   %s" % d)
+        del ex
+        n.close()
+    return {"workload": "%d Poisson requests at %.0f req/s, S uniform over %s, 9-layer CNN" % (n_requests, rate, sizes),
+            **out}
+
+
 def traffic_from_profiles(layer_key: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     PMC summary, only if it was taken on the current kernel source."""
@@ -133,6 +170,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -222,6 +260,10 @@ def main():
                           "p99_ms": float(np.percentile(lat, 99))})
         n4.close()
 
+    serving_res = None
+    if not args.no_serving and not args.no_secondary:
+        serving_res = serving(torch, dn, log=log)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
@@ -239,6 +281,7 @@ def main():
         "cpu_baseline": cpu,
         "per_conv": {str(k): v for k, v in per_layer.items()},
         "secondary": secondary,
+        "serving": serving_res,
         "kernel_source_hash": kernel_source_hash(),
         "paper_context": "3x over CPU-only for the whole Darknet application (108.28 s -> 36.28 s) on an NVIDIA "
                          "Quadro K5200 with PGI 17.10 OpenACC; context only",
