@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--pmc-driver", action="store_true",
+                    help="run only the dominant conv kernel (5 launches) and a 256 MiB device copy, "
+                         "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: inference is data-parallel with no per-forward exchange, "
@@ -195,6 +198,22 @@ def main():
     # ---------------- headline: BF16 batch 64, graph-captured forward
     log("[bench] building BF16 b64 net + autotune")
     nb, arena_b = build_net(dn, torch, net, dn.BF16, B, H, W, params)
+    if args.pmc_driver:
+        # reference copy of known size first (its counters calibrate the HBM byte counts)
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        flops = conv_flops(net, B, H, W)
+        dom = max(flops, key=lambda k: flops[k][0])
+        nb.forward(x, B, H, W, torch.empty((B,) + nb.output_shape(H, W), device="cuda"), stream)
+        torch.cuda.synchronize()
+        nb.time_layer(dom, B, H, W, 5, stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_driver": True, "copy_bytes": 256 << 20, "layer": dom,
+                          "plan": nb.layer_plan(dom, B, H, W)}))
+        return
     out_shape = nb.output_shape(H, W)
     y = torch.empty((B,) + out_shape, dtype=torch.float32, device="cuda")
     fwd = lambda: nb.forward(x, B, H, W, y, stream)

@@ -347,6 +347,10 @@ __device__ __forceinline__ i32x4 make_rsrc(const void *base, unsigned bytes)
 // drain every outstanding transfer (vmcnt(0)) before each LDS read, and the
 // pipeline below could not keep K-tiles in flight.  Completion is tracked by
 // the explicit vmcnt waits + barrier of the main loop.
+// m0 is reserved for the compiler's own LDS-DMA / message use, none of which
+// this file emits; listing it as clobbered keeps any such use correct.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void dma16(const i32x4 &rsrc, unsigned voff, const void *lds_dst)
 {
     // the destination is wave-uniform by construction; say so to the compiler
@@ -357,6 +361,7 @@ __device__ __forceinline__ void dma16(const i32x4 &rsrc, unsigned voff, const vo
                  : "s"(m0v), "v"(voff), "s"(rsrc)
                  : "memory", "m0");
 }
+#pragma clang diagnostic pop
 
 template <int DT, int BM, int BN, int WM, int WN, int NS>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
@@ -541,33 +546,53 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     const int th0 = blockIdx.y * FT_H, tw0 = blockIdx.x * FT_W;
     const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
 
-    // ---- stage the input window (zero outside the image)
+    // ---- stage the input window (zero outside the image).  Each thread
+    // walks the window with stride 256 keeping (c, row, col) incrementally
+    // (no divisions) and keeps 8 loads in flight before writing LDS.
     const int tot = a.C * LH * LW;
-    for (int e = tid; e < tot; e += 256) {
-        const int lc = e % LW, t = e / LW, lr = t % LH, c = t / LH;
-        const int hi = hi0 + lr, wi = wi0 + lc;
-        float v = 0.0f;
-        if ((unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W)
-            v = a.x[(((size_t)n * a.C + c) * a.H + hi) * a.W + wi] * a.in_inv_scale;
-        lds[e] = v;
+    {
+        int lc = tid % LW, lr = tid / LW, c = 0;
+        while (lr >= LH) { lr -= LH; ++c; }
+        const int dlc = 256 % LW, dlr = 256 / LW;
+        const float *xn = a.x + (size_t)n * a.C * a.H * a.W;
+        for (int base = 0; base < tot; base += 256 * 8) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int hi = hi0 + lr, wi = wi0 + lc;
+                const bool ok = base + j * 256 + tid < tot && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+                v[j] = ok ? xn[((size_t)c * a.H + hi) * a.W + wi] : 0.0f;
+                lc += dlc; lr += dlr;
+                if (lc >= LW) { lc -= LW; ++lr; }
+                while (lr >= LH) { lr -= LH; ++c; }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = base + j * 256 + tid;
+                if (e < tot) lds[e] = v[j] * a.in_inv_scale;
+            }
+        }
     }
 
-    // ---- this lane's K subset: LDS offsets of its taps (-1 = zero padding)
+    // ---- this lane's K subset: LDS offsets of its taps (-1 = zero padding),
+    // from a per-workgroup table built with one division per entry
     const int lrow = lane & 15, lgrp = lane >> 4;
     const int K = a.C * a.R * a.S;
+    __shared__ int tap_tab[128];
+    if (tid < 128) {
+        int o = -1;
+        if (tid < K) {
+            const int c = tid / (a.R * a.S), rs = tid - c * a.R * a.S, r = rs / a.S, sx = rs - r * a.S;
+            o = (c * LH + r) * LW + sx;
+        }
+        tap_tab[tid] = o;
+    }
+    __syncthreads();
     int toff[KSPT][KPL];
 #pragma unroll
     for (int ks = 0; ks < KSPT; ++ks)
 #pragma unroll
-        for (int e = 0; e < KPL; ++e) {
-            const int k = ks * 4 * KPL + lgrp * KPL + e;
-            int o = -1;
-            if (k < K) {
-                const int c = k / (a.R * a.S), rs = k - c * a.R * a.S, r = rs / a.S, sx = rs - r * a.S;
-                o = (c * LH + r) * LW + sx;
-            }
-            toff[ks][e] = o;
-        }
+        for (int e = 0; e < KPL; ++e) toff[ks][e] = tap_tab[ks * 4 * KPL + lgrp * KPL + e];
     // ---- B fragments for every 16-channel block, kept in registers
     const int nb_count = (a.cout_p + 15) / 16;
     u32x4 bw[MAXNB][KSPT][SPL];
