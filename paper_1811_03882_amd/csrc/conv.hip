@@ -18,6 +18,8 @@
 // of a 2x2 pooling window] -> round to the storage type -> NHWC store.
 // Pooling after the activation and after rounding are both exact because the
 // activation and the rounding are monotone non-decreasing.
+#include <type_traits>
+
 #include "dn_kernels.h"
 
 namespace dnk {
@@ -30,9 +32,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);  // v_cvt_pk_bf16_f32: round to nearest even
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint8_t f2e4m3(float f)
@@ -363,32 +363,49 @@ __device__ __forceinline__ void dma16(const i32x4 &rsrc, unsigned voff, const vo
 }
 #pragma clang diagnostic pop
 
-template <int DT, int BM, int BN, int WM, int WN, int NS>
+// SPR = 16-byte segments per LDS row (8: 128-byte K-tile, 4: 64-byte K-tile,
+// which halves a stage so that four stages of a 256x256 tile fit in LDS).
+// Row r stores logical segment s at physical segment s ^ swz(r); swz makes
+// the 16 lanes of an MFMA fragment read hit distinct banks.
+template <int SPR> __device__ __forceinline__ int seg_swz(int row)
+{
+    return SPR == 8 ? (row & 7) : ((row >> 2) & 3);
+}
+
+template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 {
-    constexpr int NW = WM * WN, NT = 64 * NW;
-    constexpr int ES = esize(DT), SEG = seg_el(DT), BKE = bk_el(DT);
-    constexpr int RSTEP = NT / 8;
-    constexpr int AR = BM / RSTEP, BR = BN / RSTEP;     // transfers per wave per K-tile
+    constexpr int NW = WM * WN;
+    constexpr int ES = esize(DT), SEG = seg_el(DT);
+    constexpr int BKE = SPR * SEG;                      // K elements per tile
+    constexpr int RPI = 64 / SPR;                       // rows filled by one wave-wide transfer
+    constexpr int RSTEP = RPI * NW;
+    constexpr int AGRP = BM / RPI, BGRP = BN / RPI;     // row groups (one transfer each) per tile
+    constexpr int AR = (AGRP + NW - 1) / NW, BR = (BGRP + NW - 1) / NW;  // transfers per wave (max)
     constexpr int LPT = AR + BR;
     constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
-    constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
-    static_assert(BM % RSTEP == 0 && BN % RSTEP == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
+    constexpr int SPL = Tr<DT>::SPL;
+    constexpr int KSPT = SPR / (4 * SPL);               // MFMA K-steps per tile
+    static_assert(KSPT >= 1 && KSPT * 4 * SPL == SPR, "K-tile / MFMA step mismatch");
+    static_assert(BM % RPI == 0 && BN % RPI == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
     static_assert(NS >= 2 && NS <= 4 && LPT * (NS - 2) < 64, "pipeline depth");
 
-    __shared__ u32x4 sA[NS][BM * 8];
-    __shared__ u32x4 sB[NS][BN * 8];
+    __shared__ u32x4 sA[NS][BM * SPR];
+    __shared__ u32x4 sB[NS][BN * SPR];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int ntn = (a.cout_p + BN - 1) / BN;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
     const int m0 = (logical / ntn) * BM, n0 = (logical % ntn) * BN;
+    // transfers this wave issues per K-tile (waves share the row groups round-robin)
+    const int my_a = (AGRP - wave + NW - 1) / NW, my_b = (BGRP - wave + NW - 1) / NW;
+    const int my_lpt = my_a + my_b;
 
-    // lane L of a transfer fills row L/8, physical segment L%8 of an 8-row
-    // group; with the row swizzle that is logical segment (L%8) ^ (L/8)
-    const int sc = (lane & 7) ^ ((lane >> 3) & 7);
-    const int rbase = tid >> 3;  // this lane's row in the wave's first group
+    // lane L of a transfer fills row L/SPR, physical segment L%SPR of its row
+    // group; with the swizzle that is the logical segment below
+    const int rbase = wave * RPI + lane / SPR;          // this lane's row in the wave's first group
+    const int sc = (lane % SPR) ^ seg_swz<SPR>(rbase);
     int a_pix[AR], a_hi[AR], a_wi[AR];
 #pragma unroll
     for (int i = 0; i < AR; ++i) {
@@ -418,8 +435,9 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     const i32x4 rw = make_rsrc(a.w, a.w_bytes);
 
     const int nkt = a.k_pad / BKE;
-    const int kt0 = blockIdx.z * a.ktiles_per_split;
-    const int kt1 = min(nkt, kt0 + a.ktiles_per_split);
+    const int tpk = bk_el(DT) / BKE;                    // tiles per 128-byte split-K unit
+    const int kt0 = blockIdx.z * a.ktiles_per_split * tpk;
+    const int kt1 = min(nkt, kt0 + a.ktiles_per_split * tpk);
     const int RS = a.R * a.S;
 
     auto issue = [&](int kt, int st) {
@@ -430,6 +448,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
         const bool kv = tap < RS;
 #pragma unroll
         for (int i = 0; i < AR; ++i) {
+            if (AGRP % NW != 0 && i == AR - 1 && i >= my_a) break;  // wave-uniform
             const int hi = a_hi[i] + r, wi = a_wi[i] + s;
             const bool ok = kv && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
             const unsigned off = ok ? (unsigned)(((a_pix[i] + hi * a.W + wi) * a.cin_p + c0) * ES) : DN_OOB;
@@ -438,6 +457,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
         const unsigned kb = (unsigned)(kt * BKE * ES);
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
+            if (BGRP % NW != 0 && i == BR - 1 && i >= my_b) break;  // wave-uniform
             const unsigned off = b_off[i] == DN_OOB ? DN_OOB : b_off[i] + kb;
             dma16(rw, off, &sB[st][(wave + i * NW) * 64]);
         }
@@ -458,9 +478,10 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     for (int kt = kt0; kt < kt1; ++kt) {
         // this wave's transfers of tile kt landed; later tiles may stay in flight
         const int after = min(NS - 2, kt1 - 1 - kt);  // tiles issued after kt so far
-        if (after >= 2) wait_vm<LPT * 2>();
-        else if (after == 1) wait_vm<LPT>();
-        else wait_vm<0>();
+        if (after == 0) wait_vm<0>();
+        else if (my_lpt == LPT) { if (after >= 2) wait_vm<LPT * 2>(); else wait_vm<LPT>(); }
+        else if (my_lpt == LPT - 1) { if (after >= 2) wait_vm<(LPT - 1) * 2>(); else wait_vm<LPT - 1>(); }
+        else { if (after >= 2) wait_vm<(LPT > 1 ? LPT - 2 : 0) * 2>(); else wait_vm<(LPT > 1 ? LPT - 2 : 0)>(); }
         lds_barrier();  // every wave's transfers landed; every wave is done with tile kt-1
         if (kt + NS - 1 < kt1) issue(kt + NS - 1, cs == 0 ? NS - 1 : cs - 1);
 #pragma unroll
@@ -472,7 +493,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) {
                     const int seg = ks * 4 * SPL + lgrp * SPL + j;
-                    af[fm][j] = sA[cs][row * 8 + (seg ^ (row & 7))];
+                    af[fm][j] = sA[cs][row * SPR + (seg ^ seg_swz<SPR>(row))];
                 }
             }
 #pragma unroll
@@ -481,7 +502,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) {
                     const int seg = ks * 4 * SPL + lgrp * SPL + j;
-                    bfr[fn][j] = sB[cs][row * 8 + (seg ^ (row & 7))];
+                    bfr[fn][j] = sB[cs][row * SPR + (seg ^ seg_swz<SPR>(row))];
                 }
             }
 #pragma unroll
@@ -539,7 +560,9 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
     constexpr int KPL = (DT == F32) ? 4 : (DT == BF16 ? 8 : 32);  // K values per lane per K-step
     constexpr int MAXNB = 4;                                      // up to 64 output channels
-    extern __shared__ float lds[];
+    using LT = typename std::conditional<DT == F32, float, typename std::conditional<DT == BF16, uint16_t, uint8_t>::type>::type;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LT *lds = reinterpret_cast<LT *>(lds_raw);  // input window in the storage type
     const int LH = (FT_H - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = blockIdx.z;
@@ -569,7 +592,12 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int e = base + j * 256 + tid;
-                if (e < tot) lds[e] = v[j] * a.in_inv_scale;
+                if (e < tot) {
+                    const float f = v[j] * a.in_inv_scale;
+                    if constexpr (DT == F32) lds[e] = f;
+                    else if constexpr (DT == BF16) lds[e] = f2bf(f);
+                    else lds[e] = f2e4m3(f);
+                }
             }
         }
     }
@@ -627,22 +655,22 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
         u32x4 af[KSPT][SPL];
 #pragma unroll
         for (int ks = 0; ks < KSPT; ++ks) {
-            float v[KPL];
+            unsigned v[KPL];  // raw storage-type bits of this lane's taps (0 = padding)
 #pragma unroll
-            for (int e = 0; e < KPL; ++e) v[e] = toff[ks][e] >= 0 ? lds[pbase + toff[ks][e]] : 0.0f;
+            for (int e = 0; e < KPL; ++e) {
+                LT t = 0;
+                if (toff[ks][e] >= 0) t = lds[pbase + toff[ks][e]];
+                if constexpr (DT == F32) v[e] = __float_as_uint(t);
+                else v[e] = (unsigned)t;
+            }
             if constexpr (DT == F32) {
-                af[ks][0] = u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3])};
+                af[ks][0] = u32x4{v[0], v[1], v[2], v[3]};
             } else if constexpr (DT == BF16) {
-                unsigned w4[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) w4[i] = (unsigned)f2bf(v[2 * i]) | ((unsigned)f2bf(v[2 * i + 1]) << 16);
-                af[ks][0] = u32x4{w4[0], w4[1], w4[2], w4[3]};
+                af[ks][0] = u32x4{v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
             } else {
                 unsigned w8[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    w8[i] = (unsigned)f2e4m3(v[4 * i]) | ((unsigned)f2e4m3(v[4 * i + 1]) << 8) |
-                            ((unsigned)f2e4m3(v[4 * i + 2]) << 16) | ((unsigned)f2e4m3(v[4 * i + 3]) << 24);
+                for (int i = 0; i < 8; ++i) w8[i] = v[4 * i] | (v[4 * i + 1] << 8) | (v[4 * i + 2] << 16) | (v[4 * i + 3] << 24);
                 af[ks][0] = u32x4{w8[0], w8[1], w8[2], w8[3]};
                 af[ks][1] = u32x4{w8[4], w8[5], w8[6], w8[7]};
             }
@@ -682,15 +710,16 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     }
 }
 
-size_t first_lds_bytes(const FirstArgs &a)
+size_t first_lds_bytes(int dt, const FirstArgs &a)
 {
-    return (size_t)a.C * ((FT_H - 1) * a.stride + a.R) * ((FT_W - 1) * a.stride + a.S) * sizeof(float);
+    const size_t n = (size_t)a.C * ((FT_H - 1) * a.stride + a.R) * ((FT_W - 1) * a.stride + a.S) * esize(dt);
+    return (n + 15) / 16 * 16;
 }
 
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
 {
     dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + FT_H - 1) / FT_H, a.batch);
-    const size_t lds = first_lds_bytes(a);
+    const size_t lds = first_lds_bytes(dt, a);
 #define DN_FIRST(D)                                                                                  \
     do {                                                                                             \
         if (a.pool) hipLaunchKernelGGL((conv_first<D, true>), grid, dim3(256), lds, s, a);           \
@@ -729,6 +758,14 @@ static const TileCfg kTiles[] = {
     {192, 256, 1, 4},  // 16: 2 stages
     {128, 256, 2, 4},  // 17: 3 stages
     {256, 128, 2, 4},  // 18: 3 stages, 8 waves
+    // 64-byte K-tiles (FP32 / BF16; FP8 falls back to 128-byte tiles)
+    {256, 256, 2, 4},  // 19: 4 stages, 8 waves
+    {192, 256, 1, 4},  // 20: 4 stages
+    {128, 256, 2, 4},  // 21: 4 stages, 8 waves
+    {256, 128, 2, 2},  // 22: 4 stages
+    // 31 x 8 = 248 tiles for M = 64*169, N = 1024 (one round on 256 CUs)
+    {352, 128, 2, 4},  // 23: 2 stages, 8 waves
+    {352, 128, 2, 2},  // 24: 2 stages, 4 waves
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -743,18 +780,22 @@ static hipError_t go(const ConvArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int NS>
+template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR = 8>
 static hipError_t go_dl(ConvArgs a, hipStream_t s)
 {
     // buffer offsets are 32-bit: the LDS-DMA kernels need tensors below 2 GiB
     const size_t xb = (size_t)a.batch * a.H * a.W * a.cin_p * esize(DT);
     const size_t wb = (size_t)a.cout_p * a.k_pad * esize(DT);
-    if (xb >= DN_OOB || wb >= DN_OOB) return go<DT, BM, BN, WM, WN>(a, s);
+    if (xb >= DN_OOB || wb >= DN_OOB) return go<DT, 128, 128, 2, 2>(a, s);  // register-staged path
     a.x_bytes = (unsigned)xb;
     a.w_bytes = (unsigned)wb;
     const int mt = (a.M + BM - 1) / BM, nt = (a.cout_p + BN - 1) / BN;
     dim3 grid(mt * nt, 1, a.splits);
-    hipLaunchKernelGGL((conv_igemm_dl<DT, BM, BN, WM, WN, NS>), grid, dim3(64 * WM * WN), 0, s, a);
+    if constexpr (DT == FP8 && SPR == 4) {
+        return go_dl<DT, BM, BN, WM, WN, NS == 4 ? 2 : NS, 8>(a, s);  // FP8 K-steps need 128-byte tiles
+    } else {
+        hipLaunchKernelGGL((conv_igemm_dl<DT, BM, BN, WM, WN, NS, SPR>), grid, dim3(64 * WM * WN), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -781,6 +822,12 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 16: return go_dl<DT, 192, 256, 1, 4, 2>(a, s);
     case 17: return go_dl<DT, 128, 256, 2, 4, 3>(a, s);
     case 18: return go_dl<DT, 256, 128, 2, 4, 3>(a, s);
+    case 19: return go_dl<DT, 256, 256, 2, 4, 4, 4>(a, s);
+    case 20: return go_dl<DT, 192, 256, 1, 4, 4, 4>(a, s);
+    case 21: return go_dl<DT, 128, 256, 2, 4, 4, 4>(a, s);
+    case 22: return go_dl<DT, 256, 128, 2, 2, 4, 4>(a, s);
+    case 23: return go_dl<DT, 352, 128, 2, 4, 2>(a, s);
+    case 24: return go_dl<DT, 352, 128, 2, 2, 2>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

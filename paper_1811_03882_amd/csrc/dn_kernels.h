@@ -63,7 +63,7 @@ struct FirstArgs {
 __host__ __device__ constexpr int first_kb(int dt) { return dt == FP8 ? 128 : 32; }
 constexpr int FIRST_MAX_COUT = 64;
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s);
-size_t first_lds_bytes(const FirstArgs &a);
+size_t first_lds_bytes(int dt, const FirstArgs &a);
 
 struct TileCfg { int bm, bn, wm, wn; };
 
