@@ -735,6 +735,229 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- halo kernel
+// Small convolutions (K = R*S*Cin_p up to HALO_KMAX elements, Cout <= 64):
+// one workgroup owns a TH x 32 output tile and every output channel.  Its
+// input window (tile + filter halo) is read from HBM once into LDS, NHWC,
+// each pixel padded to an odd number of 16-byte chunks so that the 16 lanes
+// of a fragment read hit distinct banks; the weights [cout_p][K] sit in LDS
+// as well (rows padded the same way).  The whole K loop then runs out of
+// LDS: a lane's A-fragment segment is the 16-byte channel chunk (tap, c0) of
+// its pixel, read directly from the window, so no input element is fetched
+// once per filter tap as in the gathered implicit GEMM.
+
+constexpr int HT_W = 32;
+constexpr int HALO_KMAX_BYTES = 1280;  // K * element size (the offset table holds 20 MFMA K-steps)
+
+int halo_lds_bytes(int dt, const ConvArgs &a, int th)
+{
+    const int ES = esize(dt), SEG = seg_el(dt);
+    const int kstep = 4 * (dt == FP8 ? 32 : (dt == BF16 ? 8 : 4));
+    const int K = a.R * a.S * a.cin_p;
+    const int ku = (K + kstep - 1) / kstep * kstep;
+    const int cps = a.cin_p / SEG, pst = cps | 1;
+    const int wch = ku * ES / 16, wst = wch | 1;
+    const int lh = (th - 1) * a.stride + a.R, lw = (HT_W - 1) * a.stride + a.S;
+    const int coutp = (a.cout_p + 15) / 16 * 16;
+    return (lh * lw * pst + coutp * wst) * 16;
+}
+
+constexpr int HALO_LDS_MAX = 96 * 1024;
+
+bool halo_ok(int dt, const ConvArgs &a)
+{
+    return a.R * a.S * a.cin_p * esize(dt) <= HALO_KMAX_BYTES && a.cout_p <= 64 && a.stride <= 2 &&
+           halo_lds_bytes(dt, a, 8) <= HALO_LDS_MAX;
+}
+
+// Dynamic LDS above the default per-kernel limit must be enabled per kernel.
+template <typename K> static void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int DT, bool POOL, int TH>
+__global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
+{
+    constexpr int ES = esize(DT), SEG = seg_el(DT);
+    constexpr int SPL = Tr<DT>::SPL;
+    constexpr int KPL = 4 * SPL * SEG / 4;                 // K elements per lane per MFMA step
+    constexpr int KSTEP = 4 * KPL;
+    constexpr int BLOCKS = TH * HT_W / 16, NBW = BLOCKS / 4;  // MFMA blocks per tile / per wave
+    constexpr int MAXNB = 4;
+    static_assert(KPL == SPL * SEG, "lane K chunk");
+    extern __shared__ __align__(16) unsigned char halo_raw[];
+    u32x4 *win = reinterpret_cast<u32x4 *>(halo_raw);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = lane & 15, lgrp = lane >> 4;
+    const int n = blockIdx.z, th0 = blockIdx.y * TH, tw0 = blockIdx.x * HT_W;
+    const int K = a.R * a.S * a.cin_p;
+    const int KS = (K + KSTEP - 1) / KSTEP;
+    const int cps = a.cin_p / SEG, pst = cps | 1;
+    const int wch = KS * KSTEP * ES / 16, wst = wch | 1;
+    const int LH = (TH - 1) * a.stride + a.R, LW = (HT_W - 1) * a.stride + a.S;
+    u32x4 *wlds = win + LH * LW * pst;
+    const int nb_count = (a.cout_p + 15) / 16;
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
+
+    // ---- input window -> LDS (8 loads in flight per thread)
+    {
+        const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
+        const int tot = LH * LW * cps;
+        for (int base = 0; base < tot; base += 256 * 8) {
+            u32x4 v[8];
+            int dst[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = base + j * 256 + tid;
+                const int ch = e % cps, px = e / cps, lc = px % LW, lr = px / LW;
+                const int hi = hi0 + lr, wi = wi0 + lc;
+                const bool ok = e < tot && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+                const size_t off = ok ? ((((size_t)n * a.H + hi) * a.W + wi) * a.cin_p + ch * SEG) * ES : 0;
+                v[j] = ok ? gload16(a.x, off) : z4;
+                dst[j] = e < tot ? px * pst + ch : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (dst[j] >= 0) win[dst[j]] = v[j];
+        }
+        // weights: rows [cout_p][KS*KSTEP] (K beyond k_pad reads as zero)
+        const int wtot = nb_count * 16 * wch;
+        for (int e = tid; e < wtot; e += 256) {
+            const int ch = e % wch, row = e / wch;
+            const bool ok = row < a.cout_p && (ch + 1) * 16 <= a.k_pad * ES;
+            wlds[row * wst + ch] = ok ? gload16(a.w, (size_t)row * a.k_pad * ES + ch * 16) : z4;
+        }
+    }
+    __syncthreads();
+
+    // ---- window offsets (in chunks) of every 16-byte K segment, -1 beyond K:
+    // table[(ks*4 + lane group)*SPL + j], one division per entry per workgroup
+    __shared__ int toff_tab[20 * 4 * 2];
+    for (int e = tid; e < KS * 4 * SPL; e += 256) {
+        const int j = e % SPL, g = (e / SPL) % 4, ks = e / (4 * SPL);
+        const int k = ks * KSTEP + g * KPL + j * SEG;
+        int o = -1;
+        if (k < K) {
+            const int tap = k / a.cin_p, c0 = k - tap * a.cin_p;
+            const int r = tap / a.S, sx = tap - r * a.S;
+            o = (r * LW + sx) * pst + c0 / SEG;
+        }
+        toff_tab[e] = o;
+    }
+    __syncthreads();
+
+    // ---- this wave's blocks: pixel of lane (A row) per block
+    int pbase[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+        const int b = wave + 4 * i;
+        int hl, wl;
+        if (POOL) {
+            const int rp = b / (HT_W / 8), wg = b % (HT_W / 8);
+            hl = 2 * rp + ((lrow >> 1) & 1);
+            wl = 2 * (wg * 4 + (lrow >> 2)) + (lrow & 1);
+        } else {
+            hl = b / (HT_W / 16);
+            wl = (b % (HT_W / 16)) * 16 + lrow;
+        }
+        pbase[i] = (hl * a.stride * LW + wl * a.stride) * pst;
+    }
+
+    f4 acc[NBW][MAXNB];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+        for (int j = 0; j < MAXNB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int ks = 0; ks < KS; ++ks) {
+        int toff[SPL];
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) toff[j] = toff_tab[(ks * 4 + lgrp) * SPL + j];
+        u32x4 bfr[MAXNB][SPL];
+#pragma unroll
+        for (int nb = 0; nb < MAXNB; ++nb)
+#pragma unroll
+            for (int j = 0; j < SPL; ++j)
+                bfr[nb][j] = nb < nb_count ? wlds[(nb * 16 + lrow) * wst + (ks * KSTEP + lgrp * KPL + j * SEG) / SEG] : z4;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            u32x4 af[SPL];
+#pragma unroll
+            for (int j = 0; j < SPL; ++j) af[j] = toff[j] >= 0 ? win[pbase[i] + toff[j]] : z4;
+#pragma unroll
+            for (int nb = 0; nb < MAXNB; ++nb)
+                if (nb < nb_count) mma<DT>(acc[i][nb], af, bfr[nb]);
+        }
+    }
+
+    // ---- epilogue: bias, activation, [residual], [2x2 max], round, NHWC store
+    const int Hp = a.Ho >> 1, Wp = a.Wo >> 1;
+#pragma unroll
+    for (int nb = 0; nb < MAXNB; ++nb) {
+        if (nb >= nb_count) break;
+        const int col = nb * 16 + lrow;
+        if (col >= a.cout_p) continue;
+        const float bias = a.bias[col];
+        const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            const int b = wave + 4 * i;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = activate(acc[i][nb][q] * scl + bias, a.act, a.slope);
+            if (POOL) {
+                const int rp = b / (HT_W / 8), wg = b % (HT_W / 8);
+                const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
+                if (hp < Hp && wp < Wp) {
+                    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+                    store_el<DT>(a.y, (((size_t)n * Hp + hp) * Wp + wp) * a.cout_p + col, mx * a.out_inv_scale);
+                }
+            } else {
+                const int ho = th0 + b / (HT_W / 16);
+                if (ho < a.Ho) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int wo = tw0 + (b % (HT_W / 16)) * 16 + 4 * lgrp + q;
+                        if (wo >= a.Wo) continue;
+                        const size_t o = (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + col;
+                        float r = v[q];
+                        if (a.res) r += load_el<DT>(a.res, o) * a.res_scale;
+                        store_el<DT>(a.y, o, r * a.out_inv_scale);
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s)
+{
+    if (!halo_ok(dt, a)) return hipErrorInvalidValue;
+    const int th = halo_lds_bytes(dt, a, 16) <= HALO_LDS_MAX ? 16 : 8;
+    dim3 grid((a.Wo + HT_W - 1) / HT_W, (a.Ho + th - 1) / th, a.batch);
+    const size_t lds = halo_lds_bytes(dt, a, th);
+#define DN_HALO(D)                                                                                           \
+    do {                                                                                                     \
+        if (th == 16) {                                                                                      \
+            if (a.pool) { allow_lds(conv_halo<D, true, 16>, lds); hipLaunchKernelGGL((conv_halo<D, true, 16>), grid, dim3(256), lds, s, a); } \
+            else { allow_lds(conv_halo<D, false, 16>, lds); hipLaunchKernelGGL((conv_halo<D, false, 16>), grid, dim3(256), lds, s, a); }     \
+        } else {                                                                                             \
+            if (a.pool) { allow_lds(conv_halo<D, true, 8>, lds); hipLaunchKernelGGL((conv_halo<D, true, 8>), grid, dim3(256), lds, s, a); }   \
+            else { allow_lds(conv_halo<D, false, 8>, lds); hipLaunchKernelGGL((conv_halo<D, false, 8>), grid, dim3(256), lds, s, a); }       \
+        }                                                                                                    \
+    } while (0)
+    switch (dt) {
+    case F32: DN_HALO(F32); break;
+    case BF16: DN_HALO(BF16); break;
+    case FP8: DN_HALO(FP8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DN_HALO
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- dispatch
 
 static const TileCfg kTiles[] = {
@@ -834,6 +1057,7 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
 
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s)
 {
+    if (tile == HALO_TILE) return a.splits > 1 ? hipErrorInvalidValue : launch_conv_halo(dt, a, s);
     switch (dt) {
     case F32: return dispatch<F32>(tile, a, s);
     case BF16: return dispatch<BF16>(tile, a, s);

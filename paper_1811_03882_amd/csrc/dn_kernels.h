@@ -65,6 +65,12 @@ constexpr int FIRST_MAX_COUT = 64;
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s);
 size_t first_lds_bytes(int dt, const FirstArgs &a);
 
+// Small-K convolutions can run the halo kernel instead of a GEMM tile:
+// launch_conv(dt, HALO_TILE, ...) when halo_ok() (no split-K).
+constexpr int HALO_TILE = 100;
+bool halo_ok(int dt, const ConvArgs &a);
+hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s);
+
 struct TileCfg { int bm, bn, wm, wn; };
 
 int tile_count();

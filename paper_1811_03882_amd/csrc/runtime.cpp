@@ -231,6 +231,17 @@ static ConvArgs conv_args(const dn_net *net, const Plan &p, const Op &op, char *
 
 // ---------------------------------------------------------------- planning
 
+// Can this conv op run the halo kernel (small K, <= 64 output channels)?
+static bool op_halo_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
+{
+    if (op.kind != OP_CONV || op.first) return false;
+    const dn_layer_desc &d = net->L[op.conv];
+    ConvArgs a{};
+    a.R = a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
+    a.cin_p = op.cin_p; a.cout_p = op.cout_p; a.k_pad = k_pad;
+    return halo_ok(dtype, a);
+}
+
 static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, int h, int w, Plan *out)
 {
     const int n = (int)net->L.size();
@@ -368,6 +379,9 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         if (it != net->tuned.end()) {
             op.tile = it->second.first;
             op.splits = it->second.second;
+        } else if (op_halo_ok(net, dtype, op, k_pad)) {
+            op.tile = HALO_TILE;
+            op.splits = 1;
         } else {
             heuristic_tile(M, op.cout_p, k_pad / bk_el(dtype), &op.tile, &op.splits);
         }
@@ -933,11 +947,16 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
         const int nkt = net->cw[op.conv].k_pad / bk_el(p.dtype);
         float best = 1e30f;
         int bt = op.tile, bs = op.splits;
-        for (int t = 0; t < tile_count() && rc == DN_OK; ++t) {
-            if (!tile_fits(t, op.cout_p)) continue;
-            const TileCfg tc = tile_cfg(t);
+        std::vector<int> cands;
+        if (op_halo_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
+        for (int t = 0; t < tile_count(); ++t)
+            if (tile_fits(t, op.cout_p)) cands.push_back(t);
+        for (int t : cands) {
+            if (rc != DN_OK) break;
+            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
             for (int sp = 1; sp <= 16 && rc == DN_OK; sp *= 2) {
+                if (t == HALO_TILE && sp > 1) break;
                 if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 const size_t need = sp > 1 ? (size_t)sp * M * op.cout_p * 4 : 0;
                 if (p.ws_off + need > net->arena_bytes) continue;
@@ -1069,10 +1088,15 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     heuristic_tile(M, cout_p, k_pad / bk_el(dt), &ht, &hs);
     if (t < 0) t = ht;
     if (sp <= 0) sp = (d->tile < 0) ? hs : 1;
-    if (t >= tile_count()) return fail(DN_EINVAL, "tile %d out of range", t);
+    if (t >= tile_count() && t != HALO_TILE) return fail(DN_EINVAL, "tile %d out of range", t);
     const int nkt = std::max(1, k_pad / bk_el(dt));
     if (sp > nkt) sp = nkt;
-    if (d->input_nchw) sp = 1;
+    if (d->input_nchw || t == HALO_TILE) sp = 1;
+    if (t == HALO_TILE) {
+        ConvArgs h{};
+        h.R = h.S = d->ksize; h.stride = d->stride; h.pad = d->pad; h.cin_p = cin_p; h.cout_p = cout_p; h.k_pad = k_pad;
+        if (!halo_ok(dt, h)) return fail(DN_EUNSUPPORTED, "conv desc: this shape cannot use the halo kernel");
+    }
     if (a) {
         memset(a, 0, sizeof *a);
         a->batch = d->batch; a->H = d->in_h; a->W = d->in_w; a->cin_p = cin_p;

@@ -135,6 +135,44 @@ def test_first_layer_kernel_parity(dn, dtype, shape):
         assert G.rel_l2(got, gen) < 1e-6
 
 
+# halo kernel (small K, <= 64 output channels): (batch, H, W, Cin, Cout, k, stride, pad, pool, residual)
+HALO = [
+    (2, 24, 20, 16, 32, 3, 1, 1, 1, 0),   # 9-layer c2 shape class, pooled, ragged tile
+    (1, 20, 36, 32, 64, 3, 1, 1, 0, 0),   # c3 shape class, two column tiles
+    (2, 10, 10, 64, 32, 1, 1, 0, 0, 0),   # 1x1 reduction of a residual unit
+    (1, 17, 19, 16, 48, 3, 2, 1, 0, 0),   # stride 2, odd sizes
+    (2, 12, 14, 16, 32, 3, 1, 1, 0, 1),   # fused residual add
+]
+HALO_TILE = 100
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", HALO, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8] + ("_pool" if s[8] else "") + ("_res" if s[9] else ""))
+def test_halo_kernel_parity(dn, dtype, shape):
+    b, h, w, cin, cout, k, st, pad, pool, resid = shape
+    try:
+        dn.conv_sizes(dn.conv_desc(b, h, w, cin, cout, k, st, pad, 1, 0.1, 2 if pool else 0, resid, dtype,
+                                   tile=HALO_TILE, splits=1))
+    except dn.DnError as e:
+        assert e.status == dn.DN_EUNSUPPORTED
+        pytest.skip("shape outside the halo kernel's LDS budget for this dtype")
+    p = _params(cout, cin, k, 300 + cout)
+    x = synth.make_tensor((b, cin, h, w), 14, cin, 0.0, 1.0)
+    ho, wo = (h + 2 * pad - k) // st + 1, (w + 2 * pad - k) // st + 1
+    r = synth.make_tensor((b, cout, ho, wo), 14, 99, -1.0, 1.0) if resid else None
+    ref = _oracle_conv(x, p, k, st, pad, 1, pool, res=r)
+    kw = {}
+    if dtype == dn.FP8:
+        kw = dict(in_scale=G.fp8_scale(x), out_scale=G.fp8_scale(ref), res_scale=G.fp8_scale(r) if resid else 1.0)
+    got = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, res=r, tile=HALO_TILE, splits=1, **kw)
+    err = G.rel_l2(got, ref)
+    print("halo %s %s rel_l2=%.3e" % (G.NAME[dtype], shape, err))
+    assert err < G.GATE[dtype]
+    # same reduction order as the GEMM tiles: identical bits
+    gem = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, res=r, tile=0, splits=1, **kw)
+    np.testing.assert_array_equal(got, gem)
+
+
 @pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
 def test_every_tile_config_agrees(dn, dtype):
     b, h, w, cin, cout, k = 2, 12, 14, 40, 72, 3
