@@ -172,8 +172,9 @@ typedef struct dn_conv_desc {
     int tile;        /* -1 = library heuristic, else a tile config index */
     int splits;      /* 0 = library heuristic, else split-K factor */
     int input_nchw;  /* 1: x is the NCHW FP32 network input (ingest fused into the
-                        conv; needs in_c*ksize^2 <= 32 (FP8: 128) and cout <= 64;
-                        weights packed in the order k = (c*ksize + r)*ksize + s) */
+                        conv; needs in_c*ksize <= 16, ksize <= 4 (FP8: 8),
+                        cout <= 64, stride <= 2; weights packed in the order
+                        k = r*16 + c*ksize + s) */
 } dn_conv_desc;
 
 /* Bytes of the packed weight buffer, the FP32 bias / weight-scale buffers

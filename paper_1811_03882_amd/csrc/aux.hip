@@ -64,7 +64,7 @@ template <> struct Seg<FP8> {
 // ---------------------------------------------------------------- fold + pack
 // One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
 // w' = w * scale, b' = (b - mean) * scale + beta (b' = b without BN).  The
-// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = (c*R + r)*S + s),
+// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = r*16 + c*S + s),
 // zeros in every padding.
 // FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
 
@@ -86,16 +86,20 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
         }
     }
     auto wval = [&](int k) -> double {
-        int c, tap;
-        if (compact) {
-            c = k / RS;
-            tap = k - c * RS;
-        } else {
-            tap = k / cin_p;
+        int c, r, s;
+        if (compact) {  // k = r*16 + c*S + s
+            r = k / 16;
+            const int e = k - r * 16;
+            c = e / S;
+            s = e - c * S;
+            if (co >= cout || r >= R || c >= cin) return 0.0;
+        } else {        // k = (r*S + s)*cin_p + c
+            const int tap = k / cin_p;
             c = k - tap * cin_p;
+            if (co >= cout || tap >= RS || c >= cin) return 0.0;
+            r = tap / S;
+            s = tap - r * S;
         }
-        if (co >= cout || tap >= RS || c >= cin) return 0.0;
-        const int r = tap / S, s = tap - r * S;
         return w[(((size_t)co * cin + c) * R + r) * S + s] * sc;
     };
     double qs = 1.0;

@@ -545,94 +545,128 @@ __global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
 
 // ---------------------------------------------------------------- first layer
 // The network's first convolution reads the caller's NCHW FP32 image itself
-// (the ingest is fused): a 16 x 64 output tile stages its input window in LDS
-// as FP32 (FP8: pre-divided by the input scale), every lane gathers its MFMA
-// A-fragment taps from there, and the whole Cin*R*S (<= 32, FP8 <= 128) fits
-// one K block, so B (the packed weights, compact order k = (c*R + r)*S + s)
-// stays in registers for the whole tile.  With POOL, each 16-row MFMA block
-// is four 2x2 windows, so one lane's four accumulator rows are one window.
+// (the ingest is fused).  A 16 x 64 output tile stages its input window in
+// LDS with the horizontal taps already expanded: entry (row, out-column)
+// holds the 16-element run  x[c][row][col*stride + s]  at position c*S + s
+// (zeros past C*S), in the storage type.  The K order of the packed weights
+// is k = r*16 + c*S + s, so every 16-byte K segment a lane feeds the MFMA is
+// one contiguous chunk of one run: one LDS read per segment, no per-tap
+// gather.  Chunks are XOR-swizzled by pixel so that the 16 lanes of a read
+// hit distinct banks.  B (the whole K of every output channel) stays in
+// registers for the tile.  With POOL, each 16-row MFMA block is four 2x2
+// windows, so one lane's four accumulator rows are one window.
 
 constexpr int FT_H = 16, FT_W = 64;   // conv outputs per workgroup tile
+
+__host__ __device__ constexpr int first_kstep(int dt) { return dt == FP8 ? 128 : (dt == BF16 ? 32 : 16); }
+int first_kpad(int dt, int R) { return (R * 16 + first_kstep(dt) - 1) / first_kstep(dt) * first_kstep(dt); }
+
+// 16-byte chunk slot of (window row, output column, chunk) for CPR chunks per run
+template <int CPR> __device__ __forceinline__ int run_slot(int lr, int oc, int ch)
+{
+    if constexpr (CPR == 1) return lr * FT_W + (oc ^ ((lr & 1) << 3));
+    else if constexpr (CPR == 2) return (lr * FT_W + oc) * 2 + (ch ^ (((oc >> 3) ^ lr) & 1));
+    else return (lr * FT_W + oc) * 4 + (ch ^ (((oc >> 2) ^ (lr << 1)) & 3));
+}
 
 template <int DT, bool POOL>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 {
-    constexpr int SPL = Tr<DT>::SPL, KSPT = Tr<DT>::KSPT;
-    constexpr int KPL = (DT == F32) ? 4 : (DT == BF16 ? 8 : 32);  // K values per lane per K-step
-    constexpr int MAXNB = 4;                                      // up to 64 output channels
-    using LT = typename std::conditional<DT == F32, float, typename std::conditional<DT == BF16, uint16_t, uint8_t>::type>::type;
+    constexpr int ES = esize(DT), SEG = seg_el(DT);
+    constexpr int SPL = Tr<DT>::SPL, KSTEP = first_kstep(DT);
+    constexpr int KPL = KSTEP / 4;       // K elements per lane per step
+    constexpr int CPR = ES;              // 16-byte chunks per 16-element run
+    constexpr int MAXKS = DT == FP8 ? 1 : (DT == BF16 ? 2 : 4);  // K-steps for R <= 4 (FP8: R <= 8)
+    constexpr int MAXNB = 4;             // up to 64 output channels
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    LT *lds = reinterpret_cast<LT *>(lds_raw);  // input window in the storage type
-    const int LH = (FT_H - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
+    u32x4 *win = reinterpret_cast<u32x4 *>(lds_raw);
+    const int LH = (FT_H - 1) * a.stride + a.R;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = blockIdx.z;
     const int th0 = blockIdx.y * FT_H, tw0 = blockIdx.x * FT_W;
     const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
+    const int KS = a.k_pad / KSTEP;
+    const int CS = a.C * a.S;
 
-    // ---- stage the input window (zero outside the image).  Each thread
-    // walks the window with stride 256 keeping (c, row, col) incrementally
-    // (no divisions) and keeps 8 loads in flight before writing LDS.
-    const int tot = a.C * LH * LW;
+    // ---- stage the tap-expanded window: one thread per (row, out-column),
+    // two pixels per pass so 2*C*S loads are in flight
     {
-        int lc = tid % LW, lr = tid / LW, c = 0;
-        while (lr >= LH) { lr -= LH; ++c; }
-        const int dlc = 256 % LW, dlr = 256 / LW;
         const float *xn = a.x + (size_t)n * a.C * a.H * a.W;
-        for (int base = 0; base < tot; base += 256 * 8) {
-            float v[8];
+        const int tot = LH * FT_W;
+        for (int p0 = tid; p0 < tot; p0 += 512) {
+            float v[2][16];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int hi = hi0 + lr, wi = wi0 + lc;
-                const bool ok = base + j * 256 + tid < tot && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
-                v[j] = ok ? xn[((size_t)c * a.H + hi) * a.W + wi] : 0.0f;
-                lc += dlc; lr += dlr;
-                if (lc >= LW) { lc -= LW; ++lr; }
-                while (lr >= LH) { lr -= LH; ++c; }
+            for (int u = 0; u < 2; ++u) {
+                const int p = p0 + u * 256;
+                const int lr = p / FT_W, oc = p - (p / FT_W) * FT_W;
+                const int hi = hi0 + lr;
+                const bool rok = p < tot && (unsigned)hi < (unsigned)a.H;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float f = 0.0f;
+                    if (e < CS && rok) {
+                        const int c = e / a.S, sx = e - c * a.S;
+                        const int wi = wi0 + oc * a.stride + sx;
+                        if ((unsigned)wi < (unsigned)a.W) f = xn[((size_t)c * a.H + hi) * a.W + wi];
+                    }
+                    v[u][e] = f * a.in_inv_scale;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int e = base + j * 256 + tid;
-                if (e < tot) {
-                    const float f = v[j] * a.in_inv_scale;
-                    if constexpr (DT == F32) lds[e] = f;
-                    else if constexpr (DT == BF16) lds[e] = f2bf(f);
-                    else lds[e] = f2e4m3(f);
+            for (int u = 0; u < 2; ++u) {
+                const int p = p0 + u * 256;
+                if (p >= tot) continue;
+                const int lr = p / FT_W, oc = p - (p / FT_W) * FT_W;
+#pragma unroll
+                for (int ch = 0; ch < CPR; ++ch) {
+                    u32x4 w;
+                    if constexpr (DT == F32) {
+                        w = u32x4{__float_as_uint(v[u][4 * ch]), __float_as_uint(v[u][4 * ch + 1]),
+                                  __float_as_uint(v[u][4 * ch + 2]), __float_as_uint(v[u][4 * ch + 3])};
+                    } else if constexpr (DT == BF16) {
+                        unsigned q[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            q[i] = (unsigned)f2bf(v[u][8 * ch + 2 * i]) | ((unsigned)f2bf(v[u][8 * ch + 2 * i + 1]) << 16);
+                        w = u32x4{q[0], q[1], q[2], q[3]};
+                    } else {
+                        unsigned q[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            q[i] = (unsigned)f2e4m3(v[u][4 * i]) | ((unsigned)f2e4m3(v[u][4 * i + 1]) << 8) |
+                                   ((unsigned)f2e4m3(v[u][4 * i + 2]) << 16) | ((unsigned)f2e4m3(v[u][4 * i + 3]) << 24);
+                        w = u32x4{q[0], q[1], q[2], q[3]};
+                    }
+                    win[run_slot<CPR>(lr, oc, ch)] = w;
                 }
             }
         }
     }
 
-    // ---- this lane's K subset: LDS offsets of its taps (-1 = zero padding),
-    // from a per-workgroup table built with one division per entry
+    // ---- this lane's K segments: (filter row, chunk) of each, row -1 = padding
     const int lrow = lane & 15, lgrp = lane >> 4;
-    const int K = a.C * a.R * a.S;
-    __shared__ int tap_tab[128];
-    if (tid < 128) {
-        int o = -1;
-        if (tid < K) {
-            const int c = tid / (a.R * a.S), rs = tid - c * a.R * a.S, r = rs / a.S, sx = rs - r * a.S;
-            o = (c * LH + r) * LW + sx;
+    int srow[MAXKS][SPL], schk[MAXKS][SPL];
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks)
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            const int k0 = ks * KSTEP + lgrp * KPL + j * SEG;
+            const int r = k0 / 16;
+            srow[ks][j] = (ks < KS && r < a.R) ? r : -1;
+            schk[ks][j] = (k0 % 16) / SEG;
         }
-        tap_tab[tid] = o;
-    }
-    __syncthreads();
-    int toff[KSPT][KPL];
-#pragma unroll
-    for (int ks = 0; ks < KSPT; ++ks)
-#pragma unroll
-        for (int e = 0; e < KPL; ++e) toff[ks][e] = tap_tab[ks * 4 * KPL + lgrp * KPL + e];
     // ---- B fragments for every 16-channel block, kept in registers
     const int nb_count = (a.cout_p + 15) / 16;
-    u32x4 bw[MAXNB][KSPT][SPL];
+    u32x4 bw[MAXNB][MAXKS][SPL];
 #pragma unroll
     for (int nb = 0; nb < MAXNB; ++nb)
 #pragma unroll
-        for (int ks = 0; ks < KSPT; ++ks)
+        for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
                 bw[nb][ks][j] = u32x4{0u, 0u, 0u, 0u};
-                if (nb < nb_count && nb * 16 + lrow < a.cout_p) {
-                    const size_t off = ((size_t)(nb * 16 + lrow) * a.k_pad + ks * 4 * KPL + lgrp * KPL) * esize(DT) + j * 16;
+                if (nb < nb_count && nb * 16 + lrow < a.cout_p && ks < KS) {
+                    const size_t off = ((size_t)(nb * 16 + lrow) * a.k_pad + ks * KSTEP + lgrp * KPL) * ES + j * 16;
                     bw[nb][ks][j] = gload16(a.w, off);
                 }
             }
@@ -644,43 +678,28 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
         int ho_l, wo_l;
         if (POOL) {
             const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
-            const int q = lrow, j = q >> 2;
-            ho_l = 2 * rp + ((q >> 1) & 1);
-            wo_l = 2 * (wg * 4 + j) + (q & 1);
+            ho_l = 2 * rp + ((lrow >> 1) & 1);
+            wo_l = 2 * (wg * 4 + (lrow >> 2)) + (lrow & 1);
         } else {
             ho_l = b / (FT_W / 16);
             wo_l = (b % (FT_W / 16)) * 16 + lrow;
         }
-        const int pbase = ho_l * a.stride * LW + wo_l * a.stride;
-        u32x4 af[KSPT][SPL];
+        const int lr0 = ho_l * a.stride;
+        u32x4 af[MAXKS][SPL];
 #pragma unroll
-        for (int ks = 0; ks < KSPT; ++ks) {
-            unsigned v[KPL];  // raw storage-type bits of this lane's taps (0 = padding)
+        for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
-            for (int e = 0; e < KPL; ++e) {
-                LT t = 0;
-                if (toff[ks][e] >= 0) t = lds[pbase + toff[ks][e]];
-                if constexpr (DT == F32) v[e] = __float_as_uint(t);
-                else v[e] = (unsigned)t;
+            for (int j = 0; j < SPL; ++j) {
+                const int r = srow[ks][j];
+                af[ks][j] = r >= 0 ? win[run_slot<CPR>(lr0 + r, wo_l, schk[ks][j])] : u32x4{0u, 0u, 0u, 0u};
             }
-            if constexpr (DT == F32) {
-                af[ks][0] = u32x4{v[0], v[1], v[2], v[3]};
-            } else if constexpr (DT == BF16) {
-                af[ks][0] = u32x4{v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
-            } else {
-                unsigned w8[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) w8[i] = v[4 * i] | (v[4 * i + 1] << 8) | (v[4 * i + 2] << 16) | (v[4 * i + 3] << 24);
-                af[ks][0] = u32x4{w8[0], w8[1], w8[2], w8[3]};
-                af[ks][1] = u32x4{w8[4], w8[5], w8[6], w8[7]};
-            }
-        }
 #pragma unroll
         for (int nb = 0; nb < MAXNB; ++nb) {
             if (nb >= nb_count) break;
             f4 acc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < KSPT; ++ks) mma<DT>(acc, af[ks], bw[nb][ks]);
+            for (int ks = 0; ks < MAXKS; ++ks)
+                if (ks < KS) mma<DT>(acc, af[ks], bw[nb][ks]);
             const int col = nb * 16 + lrow;
             if (col >= a.cout_p) continue;
             const float bias = a.bias[col];
@@ -712,8 +731,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 
 size_t first_lds_bytes(int dt, const FirstArgs &a)
 {
-    const size_t n = (size_t)a.C * ((FT_H - 1) * a.stride + a.R) * ((FT_W - 1) * a.stride + a.S) * esize(dt);
-    return (n + 15) / 16 * 16;
+    return (size_t)((FT_H - 1) * a.stride + a.R) * FT_W * 16 * esize(dt);
 }
 
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)

@@ -46,7 +46,7 @@ struct ConvArgs {
 };
 
 // First convolution of a network, reading the NCHW FP32 input directly.
-// Weights packed in the compact order k = (c*R + r)*S + s, k_pad = first_kb().
+// Weights packed in the order k = r*16 + c*S + s (C*S <= 16), k_pad = first_kpad().
 struct FirstArgs {
     const float *x;        // NCHW FP32 image batch
     const void *w;
@@ -59,8 +59,9 @@ struct FirstArgs {
     float in_inv_scale;    // FP8: 1 / input scale (else 1)
     float in_scale, out_inv_scale;
 };
-// K block of the first-layer kernel; a conv qualifies when C*R*S <= first_kb.
-__host__ __device__ constexpr int first_kb(int dt) { return dt == FP8 ? 128 : 32; }
+// A conv qualifies for the first-layer kernel when C*S <= 16 and R <= first_max_r.
+__host__ __device__ constexpr int first_max_r(int dt) { return dt == FP8 ? 8 : 4; }
+int first_kpad(int dt, int R);
 constexpr int FIRST_MAX_COUT = 64;
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s);
 size_t first_lds_bytes(int dt, const FirstArgs &a);
@@ -80,7 +81,7 @@ TileCfg tile_cfg(int i);
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
 
-// compact = 1 packs k = (c*R + r)*S + s (first-layer kernel), else k = (r*S + s)*cin_p + c.
+// compact = 1 packs k = r*16 + c*S + s (first-layer kernel), else k = (r*S + s)*cin_p + c.
 hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta,
                             double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,

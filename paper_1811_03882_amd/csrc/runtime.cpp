@@ -137,8 +137,8 @@ static int out_side_conv(int x, int k, int st, int pad) { return (x + 2 * pad - 
 // receptive field fits one K block and its output channels fit in registers.
 static bool first_ok(int in_c, const dn_layer_desc &d, int dt)
 {
-    return d.kind == DN_CONV && in_c * d.ksize * d.ksize <= first_kb(dt) && d.cout <= FIRST_MAX_COUT &&
-           d.stride <= 2 && d.ksize <= 7;
+    return d.kind == DN_CONV && in_c * d.ksize <= 16 && d.ksize <= first_max_r(dt) && d.cout <= FIRST_MAX_COUT &&
+           d.stride <= 2;
 }
 static bool first_eligible(const dn_net *net, int dt)
 {
@@ -420,7 +420,7 @@ static dn_status enqueue_first(const dn_net *net, const Plan &p, const Op &op, c
     a.Ho = op.pool ? op.Ho * 2 : op.Ho;
     a.Wo = op.pool ? op.Wo * 2 : op.Wo;
     a.cout_p = op.cout_p;
-    a.k_pad = first_kb(use32 ? (int)F32 : p.dtype);
+    a.k_pad = first_kpad(use32 ? (int)F32 : p.dtype, d.ksize);
     a.R = a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
     a.pool = op.pool ? 1 : 0;
     a.act = d.activation;
@@ -635,7 +635,7 @@ static dn_status pack_to(dn_net *net, int layer, int dt, const double *dw, const
     const int cin_p = cpad(dt, cw.cin);
     const bool compact = layer == 0 && first_eligible(net, dt);
     const int K = d.ksize * d.ksize * cin_p;
-    const int k_pad = compact ? first_kb(dt) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const int k_pad = compact ? first_kpad(dt, d.ksize) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
     const int cout_p = cpad(dt, d.cout);
     const size_t wb = (size_t)cout_p * k_pad * esize(dt);
     HIPCHK(hipMalloc(w, wb));
@@ -1070,8 +1070,8 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     if (d->input_nchw) {
         dn_layer_desc ld{DN_CONV, d->cout, d->ksize, d->stride, d->pad, 0, d->activation, 0};
         if (!first_ok(d->in_c, ld, dt))
-            return fail(DN_EUNSUPPORTED, "conv desc: input_nchw needs in_c*k*k <= %d, cout <= %d, stride <= 2",
-                        first_kb(dt), FIRST_MAX_COUT);
+            return fail(DN_EUNSUPPORTED, "conv desc: input_nchw needs in_c*k <= 16, k <= %d, cout <= %d, stride <= 2",
+                        first_max_r(dt), FIRST_MAX_COUT);
         if (d->residual) return fail(DN_EUNSUPPORTED, "conv desc: input_nchw with residual");
     }
     const int Ho = out_side_conv(d->in_h, d->ksize, d->stride, d->pad);
@@ -1079,7 +1079,7 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     if (Ho <= 0 || Wo <= 0) return fail(DN_EINVAL, "conv desc: output is empty");
     if (d->pool && (Ho % 2 || Wo % 2)) return fail(DN_EUNSUPPORTED, "conv desc: fused pool needs an even output (%dx%d)", Ho, Wo);
     const int K = d->ksize * d->ksize * cin_p;
-    const int k_pad = d->input_nchw ? first_kb(dt) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    const int k_pad = d->input_nchw ? first_kpad(dt, d->ksize) : (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
     const long Ml = (long)d->batch * Ho * Wo;
     if (Ml > (1L << 30)) return fail(DN_EUNSUPPORTED, "conv desc: too many output pixels");
     const int M = (int)Ml;

@@ -55,7 +55,7 @@ def test_conv_sizes_host_arithmetic(dn):
     d = dn.conv_desc(1, 13, 13, 1024, 1024, 3, 1, 1, dtype=dn.F32, tile=0, splits=4)
     assert dn.conv_sizes(d)[2] == 4 * 169 * 1024 * 4
     d = dn.conv_desc(1, 416, 416, 3, 16, 3, 1, 1, dtype=dn.BF16, pool=2, input_nchw=1)
-    assert dn.conv_sizes(d) == (16 * 32 * 2, 16 * 4, 0)
+    assert dn.conv_sizes(d) == (16 * 64 * 2, 16 * 4, 0)  # K = 3 filter rows x 16, padded to 64
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -64,7 +64,8 @@ def test_conv_sizes_host_arithmetic(dn):
     (dict(batch=0), "DN_EINVAL"),
     (dict(activation=7), "DN_EINVAL"),
     (dict(dtype=9), "DN_EINVAL"),
-    (dict(input_nchw=1, in_c=64), "DN_EUNSUPPORTED"),         # receptive field > one K block
+    (dict(input_nchw=1, in_c=64), "DN_EUNSUPPORTED"),         # C*k > 16: run does not fit
+    (dict(input_nchw=1, in_c=3, ksize=5), "DN_EUNSUPPORTED"), # 5 filter rows > 4 (BF16/FP32)
     (dict(pool=2, residual=1), "DN_EUNSUPPORTED"),
 ])
 def test_conv_desc_validation(dn, kw, status):

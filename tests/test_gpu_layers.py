@@ -113,7 +113,7 @@ FIRST = [
     (2, 32, 32, 3, 16, 3, 1, 1, 1),     # single block / plain9 stem, pooled
     (1, 40, 72, 3, 32, 3, 1, 1, 0),     # residual stem, ragged tile edges, 2 channel blocks
     (1, 30, 34, 3, 12, 3, 2, 1, 0),     # stride 2, odd channel count
-    (2, 18, 20, 1, 48, 5, 1, 2, 1),     # 5x5, single input channel, 3 channel blocks
+    (2, 18, 20, 4, 48, 3, 1, 1, 1),     # 4 input channels (C*S = 12), 3 channel blocks
 ]
 
 
