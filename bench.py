@@ -243,6 +243,20 @@ def main():
 
     secondary = []
     if not args.no_secondary:
+        # PCIe-inclusive rate: pinned host input -> H2D -> forward -> D2H, serialised on one stream
+        xh = x.cpu().pin_memory()
+        yh = torch.empty(y.shape, dtype=torch.float32).pin_memory()
+
+        def fwd_pcie():
+            x.copy_(xh, non_blocking=True)
+            nb.forward(x, B, H, W, y, stream)
+            yh.copy_(y, non_blocking=True)
+
+        with torch.cuda.stream(stream):
+            wp, pp = time_steps(torch, fwd_pcie, 10, 2, stream)
+        secondary.append({"workload": "9-layer b64 bf16 graph incl. PCIe (pinned H2D of the FP32 batch + D2H of the output)",
+                          "images_per_s": B * 10 / wp, "ms_per_step": wp * 1e3 / 10})
+        log("[bench] bf16 b64 incl. PCIe: %.3f ms/step" % (wp * 1e3 / 10))
         calib = torch.from_numpy(synth.make_input(net, 4, synth.SEED_CALIB).astype(np.float32)).cuda()
         for name, dt in (("fp8", dn.FP8), ("f32", dn.F32)):
             log("[bench] %s b64" % name)

@@ -172,9 +172,10 @@ typedef struct dn_conv_desc {
     int tile;        /* -1 = library heuristic, else a tile config index */
     int splits;      /* 0 = library heuristic, else split-K factor */
     int input_nchw;  /* 1: x is the NCHW FP32 network input (ingest fused into the
-                        conv; needs in_c*ksize <= 16, ksize <= 4 (FP8: 8),
-                        cout <= 64, stride <= 2; weights packed in the order
-                        k = r*16 + c*ksize + s) */
+                        conv; needs CP*ksize <= 16 where CP = in_c rounded
+                        up to 4, 8 or 16 (in_c <= 16), ksize <= 4, cout <= 64,
+                        stride <= 2, else DN_EUNSUPPORTED; weights packed in
+                        the order k = r*16 + s*CP + c) */
 } dn_conv_desc;
 
 /* Bytes of the packed weight buffer, the FP32 bias / weight-scale buffers

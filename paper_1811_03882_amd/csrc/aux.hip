@@ -64,7 +64,8 @@ template <> struct Seg<FP8> {
 // ---------------------------------------------------------------- fold + pack
 // One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
 // w' = w * scale, b' = (b - mean) * scale + beta (b' = b without BN).  The
-// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = r*16 + c*S + s),
+// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = r*16 + s*CP + c,
+// CP = first_cp(cin)),
 // zeros in every padding.
 // FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
 
@@ -87,12 +88,13 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
     }
     auto wval = [&](int k) -> double {
         int c, r, s;
-        if (compact) {  // k = r*16 + c*S + s
+        if (compact) {  // k = r*16 + s*CP + c
+            const int cp = first_cp(cin);
             r = k / 16;
             const int e = k - r * 16;
-            c = e / S;
-            s = e - c * S;
-            if (co >= cout || r >= R || c >= cin) return 0.0;
+            s = e / cp;
+            c = e - s * cp;
+            if (co >= cout || r >= R || s >= S || c >= cin) return 0.0;
         } else {        // k = (r*S + s)*cin_p + c
             const int tap = k / cin_p;
             c = k - tap * cin_p;

@@ -543,155 +543,192 @@ __global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
     }
 }
 
+// Dynamic LDS above the default per-kernel limit must be enabled per kernel.
+template <typename K> static void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 // ---------------------------------------------------------------- first layer
 // The network's first convolution reads the caller's NCHW FP32 image itself
-// (the ingest is fused).  A 16 x 64 output tile stages its input window in
-// LDS with the horizontal taps already expanded: entry (row, out-column)
-// holds the 16-element run  x[c][row][col*stride + s]  at position c*S + s
-// (zeros past C*S), in the storage type.  The K order of the packed weights
-// is k = r*16 + c*S + s, so every 16-byte K segment a lane feeds the MFMA is
-// one contiguous chunk of one run: one LDS read per segment, no per-tap
-// gather.  Chunks are XOR-swizzled by pixel so that the 16 lanes of a read
-// hit distinct banks.  B (the whole K of every output channel) stays in
-// registers for the tile.  With POOL, each 16-row MFMA block is four 2x2
-// windows, so one lane's four accumulator rows are one window.
+// (the ingest is fused).  A th x 64 output tile (th = 16, or 8 when the window
+// of 16 rows would not fit in LDS) stages its input window in LDS as NHWC in
+// the storage type, channels padded to CP = 4, 8 or 16 with zeros.  The packed
+// weights use the K order k = r*16 + s*CP + c (CP*S <= 16), so the 16 K
+// elements of filter row r for output pixel (ho, wo) are the window pixels
+// (ho*stride + r, wo*stride + s), s < S: a contiguous span of the window, read
+// straight into the MFMA operand (read units past S are zero, matching zero
+// weights).  The weights are operand A and stay in registers for the tile;
+// pixels are operand B, so a lane's accumulator holds four consecutive output
+// channels of one pixel and leaves with one vector store.  With POOL a
+// 16-pixel block is four 2x2 windows on lanes 4w..4w+3, reduced by two quad
+// shuffles.
 
-constexpr int FT_H = 16, FT_W = 64;   // conv outputs per workgroup tile
+constexpr int FT_W = 64;   // conv output columns per workgroup tile
 
 __host__ __device__ constexpr int first_kstep(int dt) { return dt == FP8 ? 128 : (dt == BF16 ? 32 : 16); }
 int first_kpad(int dt, int R) { return (R * 16 + first_kstep(dt) - 1) / first_kstep(dt) * first_kstep(dt); }
 
-// 16-byte chunk slot of (window row, output column, chunk) for CPR chunks per run
-template <int CPR> __device__ __forceinline__ int run_slot(int lr, int oc, int ch)
+// CP floats -> one window pixel in the storage type (CP*esize bytes at dst)
+template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned char *dst, const float *v, float sc)
 {
-    if constexpr (CPR == 1) return lr * FT_W + (oc ^ ((lr & 1) << 3));
-    else if constexpr (CPR == 2) return (lr * FT_W + oc) * 2 + (ch ^ (((oc >> 3) ^ lr) & 1));
-    else return (lr * FT_W + oc) * 4 + (ch ^ (((oc >> 2) ^ (lr << 1)) & 3));
+    constexpr int NW = CP * esize(DT) / 4;  // 32-bit words
+    unsigned w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        if constexpr (DT == F32) {
+            w[i] = __float_as_uint(v[i] * sc);
+        } else if constexpr (DT == BF16) {
+            w[i] = (unsigned)f2bf(v[2 * i] * sc) | ((unsigned)f2bf(v[2 * i + 1] * sc) << 16);
+        } else {
+            w[i] = (unsigned)f2e4m3(v[4 * i] * sc) | ((unsigned)f2e4m3(v[4 * i + 1] * sc) << 8) |
+                   ((unsigned)f2e4m3(v[4 * i + 2] * sc) << 16) | ((unsigned)f2e4m3(v[4 * i + 3] * sc) << 24);
+        }
+    }
+    if constexpr (NW == 1) {
+        *reinterpret_cast<unsigned *>(dst) = w[0];
+    } else if constexpr (NW == 2) {
+        *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NW / 4; ++q)
+            reinterpret_cast<u32x4 *>(dst)[q] = u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+    }
 }
 
-template <int DT, bool POOL>
+// four consecutive channels, FP32 values -> storage type, one store
+template <int DT> __device__ __forceinline__ void store4(void *y, size_t idx, const float *v)
+{
+    if constexpr (DT == F32) {
+        *reinterpret_cast<float4 *>((float *)y + idx) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (DT == BF16) {
+        *reinterpret_cast<uint2 *>((uint16_t *)y + idx) =
+            make_uint2((unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16), (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16));
+    } else {
+        *reinterpret_cast<unsigned *>((uint8_t *)y + idx) = (unsigned)f2e4m3(v[0]) | ((unsigned)f2e4m3(v[1]) << 8) |
+                                                            ((unsigned)f2e4m3(v[2]) << 16) | ((unsigned)f2e4m3(v[3]) << 24);
+    }
+}
+
+// max with the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (0x4E) of its quad
+template <int CTRL> __device__ __forceinline__ float quad_max(float v)
+{
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false)));
+}
+
+template <int DT, bool POOL, int CP>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 {
     constexpr int ES = esize(DT), SEG = seg_el(DT);
     constexpr int SPL = Tr<DT>::SPL, KSTEP = first_kstep(DT);
-    constexpr int KPL = KSTEP / 4;       // K elements per lane per step
-    constexpr int CPR = ES;              // 16-byte chunks per 16-element run
-    constexpr int MAXKS = DT == FP8 ? 1 : (DT == BF16 ? 2 : 4);  // K-steps for R <= 4 (FP8: R <= 8)
-    constexpr int MAXNB = 4;             // up to 64 output channels
+    constexpr int KPL = KSTEP / 4;                               // K elements per lane per step
+    constexpr int PIXB = CP * ES;                                // bytes per window pixel
+    constexpr int UB = PIXB < 16 ? PIXB : 16;                    // LDS read unit
+    constexpr int UPS = 16 / UB;                                 // read units per 16-byte segment
+    constexpr int MAXKS = DT == FP8 ? 1 : (DT == BF16 ? 2 : 4);  // K-steps for R <= FIRST_MAX_R
+    constexpr int MAXNB = FIRST_MAX_COUT / 16;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    u32x4 *win = reinterpret_cast<u32x4 *>(lds_raw);
-    const int LH = (FT_H - 1) * a.stride + a.R;
+    const int LH = (a.th - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = lane & 15, lgrp = lane >> 4;
     const int n = blockIdx.z;
-    const int th0 = blockIdx.y * FT_H, tw0 = blockIdx.x * FT_W;
+    const int th0 = blockIdx.y * a.th, tw0 = blockIdx.x * FT_W;
     const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
     const int KS = a.k_pad / KSTEP;
-    const int CS = a.C * a.S;
 
-    // ---- stage the tap-expanded window: one thread per (row, out-column),
-    // two pixels per pass so 2*C*S loads are in flight
+    // ---- stage the window: thread per pixel, PB pixels (all their channel
+    // loads) in flight per thread, (row, col) advanced incrementally
     {
-        const float *xn = a.x + (size_t)n * a.C * a.H * a.W;
-        const int tot = LH * FT_W;
-        for (int p0 = tid; p0 < tot; p0 += 512) {
-            float v[2][16];
+        constexpr int PB = 32 / CP;
+        const int npix = LH * LW;
+        const size_t plane = (size_t)a.H * a.W;
+        const float *xn = a.x + (size_t)n * a.C * plane;
+        int lr = tid / LW, lc = tid % LW;
+        const int dlr = 256 / LW, dlc = 256 % LW;
+        for (int base = 0; base < npix; base += 256 * PB) {
+            float v[PB][CP];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int p = p0 + u * 256;
-                const int lr = p / FT_W, oc = p - (p / FT_W) * FT_W;
-                const int hi = hi0 + lr;
-                const bool rok = p < tot && (unsigned)hi < (unsigned)a.H;
+            for (int j = 0; j < PB; ++j) {
+                const int hi = hi0 + lr, wi = wi0 + lc;
+                const bool ok = base + j * 256 + tid < npix && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+                const size_t o = ok ? (size_t)hi * a.W + wi : 0;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    float f = 0.0f;
-                    if (e < CS && rok) {
-                        const int c = e / a.S, sx = e - c * a.S;
-                        const int wi = wi0 + oc * a.stride + sx;
-                        if ((unsigned)wi < (unsigned)a.W) f = xn[((size_t)c * a.H + hi) * a.W + wi];
-                    }
-                    v[u][e] = f * a.in_inv_scale;
-                }
+                for (int c = 0; c < CP; ++c) v[j][c] = (ok && c < a.C) ? xn[o + c * plane] : 0.0f;
+                lc += dlc; lr += dlr;
+                if (lc >= LW) { lc -= LW; ++lr; }
             }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int p = p0 + u * 256;
-                if (p >= tot) continue;
-                const int lr = p / FT_W, oc = p - (p / FT_W) * FT_W;
-#pragma unroll
-                for (int ch = 0; ch < CPR; ++ch) {
-                    u32x4 w;
-                    if constexpr (DT == F32) {
-                        w = u32x4{__float_as_uint(v[u][4 * ch]), __float_as_uint(v[u][4 * ch + 1]),
-                                  __float_as_uint(v[u][4 * ch + 2]), __float_as_uint(v[u][4 * ch + 3])};
-                    } else if constexpr (DT == BF16) {
-                        unsigned q[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            q[i] = (unsigned)f2bf(v[u][8 * ch + 2 * i]) | ((unsigned)f2bf(v[u][8 * ch + 2 * i + 1]) << 16);
-                        w = u32x4{q[0], q[1], q[2], q[3]};
-                    } else {
-                        unsigned q[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            q[i] = (unsigned)f2e4m3(v[u][4 * i]) | ((unsigned)f2e4m3(v[u][4 * i + 1]) << 8) |
-                                   ((unsigned)f2e4m3(v[u][4 * i + 2]) << 16) | ((unsigned)f2e4m3(v[u][4 * i + 3]) << 24);
-                        w = u32x4{q[0], q[1], q[2], q[3]};
-                    }
-                    win[run_slot<CPR>(lr, oc, ch)] = w;
-                }
+            for (int j = 0; j < PB; ++j) {
+                const int p = base + j * 256 + tid;
+                if (p < npix) put_pixel<DT, CP>(lds_raw + (size_t)p * PIXB, v[j], a.in_inv_scale);
             }
         }
     }
 
-    // ---- this lane's K segments: (filter row, chunk) of each, row -1 = padding
-    const int lrow = lane & 15, lgrp = lane >> 4;
-    int srow[MAXKS][SPL], schk[MAXKS][SPL];
+    // ---- this lane's window offsets (bytes, relative to its pixel) for every
+    // read unit of its K segments; -1 where the unit lies past row R or tap S
+    int uoff[MAXKS][SPL][UPS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
-        for (int j = 0; j < SPL; ++j) {
-            const int k0 = ks * KSTEP + lgrp * KPL + j * SEG;
-            const int r = k0 / 16;
-            srow[ks][j] = (ks < KS && r < a.R) ? r : -1;
-            schk[ks][j] = (k0 % 16) / SEG;
-        }
-    // ---- B fragments for every 16-channel block, kept in registers
+        for (int j = 0; j < SPL; ++j)
+#pragma unroll
+            for (int u = 0; u < UPS; ++u) {
+                const int k0 = ks * KSTEP + lgrp * KPL + j * SEG;
+                const int r = k0 / 16, rb = (k0 % 16) * ES + u * UB;  // byte within the run
+                const int s = rb / PIXB;
+                uoff[ks][j][u] = (ks < KS && r < a.R && s < a.S) ? (r * LW + s) * PIXB + rb % PIXB : -1;
+            }
+    // ---- A fragments (weights) for every 16-channel block, kept in registers
     const int nb_count = (a.cout_p + 15) / 16;
-    u32x4 bw[MAXNB][MAXKS][SPL];
+    u32x4 aw[MAXNB][MAXKS][SPL];
 #pragma unroll
     for (int nb = 0; nb < MAXNB; ++nb)
 #pragma unroll
         for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
-                bw[nb][ks][j] = u32x4{0u, 0u, 0u, 0u};
+                aw[nb][ks][j] = u32x4{0u, 0u, 0u, 0u};
                 if (nb < nb_count && nb * 16 + lrow < a.cout_p && ks < KS) {
                     const size_t off = ((size_t)(nb * 16 + lrow) * a.k_pad + ks * KSTEP + lgrp * KPL) * ES + j * 16;
-                    bw[nb][ks][j] = gload16(a.w, off);
+                    aw[nb][ks][j] = gload16(a.w, off);
                 }
             }
     __syncthreads();
 
-    constexpr int BLOCKS = FT_H * FT_W / 16;  // 16-pixel MFMA blocks per tile
-    for (int b = wave; b < BLOCKS; b += 4) {
-        // this lane's pixel (A row) in the tile
+    const int blocks = a.th * FT_W / 16;  // 16-pixel MFMA blocks per tile
+    for (int b = wave; b < blocks; b += 4) {
+        // this lane's pixel (B column) in the tile
         int ho_l, wo_l;
         if (POOL) {
-            const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
-            ho_l = 2 * rp + ((lrow >> 1) & 1);
-            wo_l = 2 * (wg * 4 + (lrow >> 2)) + (lrow & 1);
+            const int rp = b / (FT_W / 8), wg = b % (FT_W / 8), q = lrow & 3;
+            ho_l = 2 * rp + (q >> 1);
+            wo_l = 2 * (wg * 4 + (lrow >> 2)) + (q & 1);
         } else {
             ho_l = b / (FT_W / 16);
             wo_l = (b % (FT_W / 16)) * 16 + lrow;
         }
-        const int lr0 = ho_l * a.stride;
-        u32x4 af[MAXKS][SPL];
+        const unsigned char *px = lds_raw + (size_t)(ho_l * a.stride * LW + wo_l * a.stride) * PIXB;
+        u32x4 bf[MAXKS][SPL];
 #pragma unroll
         for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
-                const int r = srow[ks][j];
-                af[ks][j] = r >= 0 ? win[run_slot<CPR>(lr0 + r, wo_l, schk[ks][j])] : u32x4{0u, 0u, 0u, 0u};
+                unsigned wv[4];
+#pragma unroll
+                for (int u = 0; u < UPS; ++u) {
+                    const int o = uoff[ks][j][u];
+                    if constexpr (UB == 16) {
+                        const u32x4 t = o >= 0 ? *reinterpret_cast<const u32x4 *>(px + o) : u32x4{0u, 0u, 0u, 0u};
+                        wv[0] = t.x; wv[1] = t.y; wv[2] = t.z; wv[3] = t.w;
+                    } else if constexpr (UB == 8) {
+                        const uint2 t = o >= 0 ? *reinterpret_cast<const uint2 *>(px + o) : make_uint2(0u, 0u);
+                        wv[2 * u] = t.x; wv[2 * u + 1] = t.y;
+                    } else {
+                        wv[u] = o >= 0 ? *reinterpret_cast<const unsigned *>(px + o) : 0u;
+                    }
+                }
+                bf[ks][j] = u32x4{wv[0], wv[1], wv[2], wv[3]};
             }
 #pragma unroll
         for (int nb = 0; nb < MAXNB; ++nb) {
@@ -699,49 +736,72 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
             f4 acc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < MAXKS; ++ks)
-                if (ks < KS) mma<DT>(acc, af[ks], bw[nb][ks]);
-            const int col = nb * 16 + lrow;
-            if (col >= a.cout_p) continue;
-            const float bias = a.bias[col];
-            const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
+                if (ks < KS) mma<DT>(acc, aw[nb][ks], bf[ks]);
+            // acc[i]: channel ch0 + i of this lane's pixel
+            const int ch0 = nb * 16 + 4 * lgrp;
+            const bool live = ch0 < a.cout_p;  // cout_p is a multiple of 4
             float v[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl + bias, a.act, a.slope);
+            for (int i = 0; i < 4; ++i) {
+                const float bias = live ? a.bias[ch0 + i] : 0.0f;
+                const float scl = (DT == FP8 && live) ? a.wscale[ch0 + i] * a.in_scale : 1.0f;
+                v[i] = activate(acc[i] * scl + bias, a.act, a.slope) * a.out_inv_scale;
+            }
             if (POOL) {
-                const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
-                const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
-                if (hp < (a.Ho >> 1) && wp < (a.Wo >> 1)) {
-                    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
-                    store_el<DT>(a.y, (((size_t)n * (a.Ho >> 1) + hp) * (a.Wo >> 1) + wp) * a.cout_p + col, mx * a.out_inv_scale);
-                }
-            } else {
-                const int ho = th0 + ho_l;
-                if (ho < a.Ho) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int wo = tw0 + (b % (FT_W / 16)) * 16 + 4 * lgrp + i;
-                        if (wo < a.Wo)
-                            store_el<DT>(a.y, (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + col, v[i] * a.out_inv_scale);
-                    }
-                }
+                for (int i = 0; i < 4; ++i) v[i] = quad_max<0x4E>(quad_max<0xB1>(v[i]));
+                const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
+                const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + (lrow >> 2);
+                if (live && (lrow & 3) == 0 && hp < (a.Ho >> 1) && wp < (a.Wo >> 1))
+                    store4<DT>(a.y, (((size_t)n * (a.Ho >> 1) + hp) * (a.Wo >> 1) + wp) * a.cout_p + ch0, v);
+            } else {
+                const int ho = th0 + ho_l, wo = tw0 + wo_l;
+                if (live && ho < a.Ho && wo < a.Wo)
+                    store4<DT>(a.y, (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + ch0, v);
             }
         }
     }
 }
 
-size_t first_lds_bytes(int dt, const FirstArgs &a)
+static size_t first_lds_for(int C, int R, int S, int stride, int th, int dt)
 {
-    return (size_t)((FT_H - 1) * a.stride + a.R) * FT_W * 16 * esize(dt);
+    const int LH = (th - 1) * stride + R, LW = (FT_W - 1) * stride + S;
+    return (size_t)LH * LW * first_cp(C) * esize(dt);
+}
+static int first_tile_h(int dt, int C, int R, int S, int stride)
+{
+    return first_lds_for(C, R, S, stride, 16, dt) <= FIRST_LDS_MAX ? 16 : 8;
+}
+size_t first_lds_bytes(int dt, int C, int R, int S, int stride)
+{
+    return first_lds_for(C, R, S, stride, first_tile_h(dt, C, R, S, stride), dt);
 }
 
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
 {
-    dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + FT_H - 1) / FT_H, a.batch);
-    const size_t lds = first_lds_bytes(dt, a);
+    FirstArgs b = a;
+    b.th = first_tile_h(dt, a.C, a.R, a.S, a.stride);
+    const size_t lds = first_lds_for(a.C, a.R, a.S, a.stride, b.th, dt);
+    if (lds > FIRST_LDS_MAX || a.R > FIRST_MAX_R || a.C > 16 || first_cp(a.C) * a.S > 16 || a.cout_p > FIRST_MAX_COUT ||
+        a.stride > 2 || (a.cout_p & 3))
+        return hipErrorInvalidValue;
+    dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + b.th - 1) / b.th, a.batch);
+#define DN_FIRST_CP(D, P, C)                                                                         \
+    do {                                                                                             \
+        allow_lds(conv_first<D, P, C>, lds);                                                         \
+        hipLaunchKernelGGL((conv_first<D, P, C>), grid, dim3(256), lds, s, b);                       \
+    } while (0)
+#define DN_FIRST_P(D, P)                                                                             \
+    do {                                                                                             \
+        const int cp = first_cp(a.C);                                                                \
+        if (cp == 4) DN_FIRST_CP(D, P, 4);                                                           \
+        else if (cp == 8) DN_FIRST_CP(D, P, 8);                                                      \
+        else DN_FIRST_CP(D, P, 16);                                                                  \
+    } while (0)
 #define DN_FIRST(D)                                                                                  \
     do {                                                                                             \
-        if (a.pool) hipLaunchKernelGGL((conv_first<D, true>), grid, dim3(256), lds, s, a);           \
-        else hipLaunchKernelGGL((conv_first<D, false>), grid, dim3(256), lds, s, a);                 \
+        if (b.pool) DN_FIRST_P(D, true);                                                             \
+        else DN_FIRST_P(D, false);                                                                   \
     } while (0)
     switch (dt) {
     case F32: DN_FIRST(F32); break;
@@ -750,6 +810,8 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     default: return hipErrorInvalidValue;
     }
 #undef DN_FIRST
+#undef DN_FIRST_P
+#undef DN_FIRST_CP
     return hipGetLastError();
 }
 
@@ -788,13 +850,8 @@ bool halo_ok(int dt, const ConvArgs &a)
            halo_lds_bytes(dt, a, 8) <= HALO_LDS_MAX;
 }
 
-// Dynamic LDS above the default per-kernel limit must be enabled per kernel.
-template <typename K> static void allow_lds(K kernel, size_t bytes)
-{
-    if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
 
-template <int DT, bool POOL, int TH>
+template <int DT, bool POOL, int TH, int NB>
 __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
 {
     constexpr int ES = esize(DT), SEG = seg_el(DT);
@@ -802,7 +859,7 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     constexpr int KPL = 4 * SPL * SEG / 4;                 // K elements per lane per MFMA step
     constexpr int KSTEP = 4 * KPL;
     constexpr int BLOCKS = TH * HT_W / 16, NBW = BLOCKS / 4;  // MFMA blocks per tile / per wave
-    constexpr int MAXNB = 4;
+    constexpr int MAXNB = NB;                                 // 16-channel output blocks
     static_assert(KPL == SPL * SEG, "lane K chunk");
     extern __shared__ __align__(16) unsigned char halo_raw[];
     u32x4 *win = reinterpret_cast<u32x4 *>(halo_raw);
@@ -816,7 +873,7 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     const int wch = KS * KSTEP * ES / 16, wst = wch | 1;
     const int LH = (TH - 1) * a.stride + a.R, LW = (HT_W - 1) * a.stride + a.S;
     u32x4 *wlds = win + LH * LW * pst;
-    const int nb_count = (a.cout_p + 15) / 16;
+    constexpr int nb_count = NB;
     const u32x4 z4 = {0u, 0u, 0u, 0u};
 
     // ---- input window -> LDS (8 loads in flight per thread)
@@ -950,30 +1007,38 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     }
 }
 
+template <int DT, bool POOL, int TH>
+static hipError_t go_halo(const ConvArgs &a, dim3 grid, size_t lds, hipStream_t s)
+{
+    switch ((a.cout_p + 15) / 16) {
+    case 1: allow_lds(conv_halo<DT, POOL, TH, 1>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 1>), grid, dim3(256), lds, s, a); break;
+    case 2: allow_lds(conv_halo<DT, POOL, TH, 2>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 2>), grid, dim3(256), lds, s, a); break;
+    case 3: allow_lds(conv_halo<DT, POOL, TH, 3>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 3>), grid, dim3(256), lds, s, a); break;
+    case 4: allow_lds(conv_halo<DT, POOL, TH, 4>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 4>), grid, dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t go_halo_dt(const ConvArgs &a, int th, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (th == 16) return a.pool ? go_halo<DT, true, 16>(a, grid, lds, s) : go_halo<DT, false, 16>(a, grid, lds, s);
+    return a.pool ? go_halo<DT, true, 8>(a, grid, lds, s) : go_halo<DT, false, 8>(a, grid, lds, s);
+}
+
 hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s)
 {
     if (!halo_ok(dt, a)) return hipErrorInvalidValue;
     const int th = halo_lds_bytes(dt, a, 16) <= HALO_LDS_MAX ? 16 : 8;
     dim3 grid((a.Wo + HT_W - 1) / HT_W, (a.Ho + th - 1) / th, a.batch);
     const size_t lds = halo_lds_bytes(dt, a, th);
-#define DN_HALO(D)                                                                                           \
-    do {                                                                                                     \
-        if (th == 16) {                                                                                      \
-            if (a.pool) { allow_lds(conv_halo<D, true, 16>, lds); hipLaunchKernelGGL((conv_halo<D, true, 16>), grid, dim3(256), lds, s, a); } \
-            else { allow_lds(conv_halo<D, false, 16>, lds); hipLaunchKernelGGL((conv_halo<D, false, 16>), grid, dim3(256), lds, s, a); }     \
-        } else {                                                                                             \
-            if (a.pool) { allow_lds(conv_halo<D, true, 8>, lds); hipLaunchKernelGGL((conv_halo<D, true, 8>), grid, dim3(256), lds, s, a); }   \
-            else { allow_lds(conv_halo<D, false, 8>, lds); hipLaunchKernelGGL((conv_halo<D, false, 8>), grid, dim3(256), lds, s, a); }       \
-        }                                                                                                    \
-    } while (0)
     switch (dt) {
-    case F32: DN_HALO(F32); break;
-    case BF16: DN_HALO(BF16); break;
-    case FP8: DN_HALO(FP8); break;
+    case F32: return go_halo_dt<F32>(a, th, grid, lds, s);
+    case BF16: return go_halo_dt<BF16>(a, th, grid, lds, s);
+    case FP8: return go_halo_dt<FP8>(a, th, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
-#undef DN_HALO
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -1007,6 +1072,8 @@ static const TileCfg kTiles[] = {
     // 31 x 8 = 248 tiles for M = 64*169, N = 1024 (one round on 256 CUs)
     {352, 128, 2, 4},  // 23: 2 stages, 8 waves
     {352, 128, 2, 2},  // 24: 2 stages, 4 waves
+    {352, 128, 2, 8},  // 25: 2 stages, 16 waves (4 per SIMD)
+    {256, 256, 2, 8},  // 26: 2 stages, 16 waves
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -1069,6 +1136,8 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 22: return go_dl<DT, 256, 128, 2, 2, 4, 4>(a, s);
     case 23: return go_dl<DT, 352, 128, 2, 4, 2>(a, s);
     case 24: return go_dl<DT, 352, 128, 2, 2, 2>(a, s);
+    case 25: return go_dl<DT, 352, 128, 2, 8, 2>(a, s);
+    case 26: return go_dl<DT, 256, 256, 2, 8, 2>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

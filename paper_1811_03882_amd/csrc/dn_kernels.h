@@ -46,7 +46,7 @@ struct ConvArgs {
 };
 
 // First convolution of a network, reading the NCHW FP32 input directly.
-// Weights packed in the order k = r*16 + c*S + s (C*S <= 16), k_pad = first_kpad().
+// Weights packed in the order k = r*16 + s*CP + c, CP = first_cp(C), k_pad = first_kpad().
 struct FirstArgs {
     const float *x;        // NCHW FP32 image batch
     const void *w;
@@ -58,13 +58,18 @@ struct FirstArgs {
     float slope;
     float in_inv_scale;    // FP8: 1 / input scale (else 1)
     float in_scale, out_inv_scale;
+    int th;                // output rows per tile (set by launch_conv_first)
 };
-// A conv qualifies for the first-layer kernel when C*S <= 16 and R <= first_max_r.
-__host__ __device__ constexpr int first_max_r(int dt) { return dt == FP8 ? 8 : 4; }
-int first_kpad(int dt, int R);
+// Channels of one staged window pixel: C rounded up to 4, 8 or 16.
+__host__ __device__ constexpr int first_cp(int C) { return C <= 4 ? 4 : (C <= 8 ? 8 : 16); }
+// A conv qualifies for the first-layer kernel when C <= 16, first_cp(C)*S <= 16,
+// R <= FIRST_MAX_R, cout <= FIRST_MAX_COUT and stride <= 2.
+constexpr int FIRST_MAX_R = 4;
 constexpr int FIRST_MAX_COUT = 64;
+constexpr size_t FIRST_LDS_MAX = 160 * 1024;
+int first_kpad(int dt, int R);
 hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s);
-size_t first_lds_bytes(int dt, const FirstArgs &a);
+size_t first_lds_bytes(int dt, int C, int R, int S, int stride);
 
 // Small-K convolutions can run the halo kernel instead of a GEMM tile:
 // launch_conv(dt, HALO_TILE, ...) when halo_ok() (no split-K).
@@ -81,7 +86,8 @@ TileCfg tile_cfg(int i);
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
 
-// compact = 1 packs k = r*16 + c*S + s (first-layer kernel), else k = (r*S + s)*cin_p + c.
+// compact = 1 packs k = r*16 + s*first_cp(cin) + c (first-layer kernel; cin_p unused),
+// else k = (r*S + s)*cin_p + c.
 hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta,
                             double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,

@@ -133,12 +133,14 @@ struct dn_net {
 
 static int out_side_conv(int x, int k, int st, int pad) { return (x + 2 * pad - k) / st + 1; }
 
-// The network's first conv takes the fused-ingest kernel when its whole
-// receptive field fits one K block and its output channels fit in registers.
+// The network's first conv takes the fused-ingest kernel when one filter row
+// of every input channel fits a 16-element run of the staged window and its
+// output channels fit in registers.
 static bool first_ok(int in_c, const dn_layer_desc &d, int dt)
 {
-    return d.kind == DN_CONV && in_c * d.ksize <= 16 && d.ksize <= first_max_r(dt) && d.cout <= FIRST_MAX_COUT &&
-           d.stride <= 2;
+    (void)dt;
+    return d.kind == DN_CONV && in_c <= 16 && first_cp(in_c) * d.ksize <= 16 && d.ksize <= FIRST_MAX_R &&
+           d.cout <= FIRST_MAX_COUT && d.stride <= 2;
 }
 static bool first_eligible(const dn_net *net, int dt)
 {
@@ -1070,8 +1072,8 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     if (d->input_nchw) {
         dn_layer_desc ld{DN_CONV, d->cout, d->ksize, d->stride, d->pad, 0, d->activation, 0};
         if (!first_ok(d->in_c, ld, dt))
-            return fail(DN_EUNSUPPORTED, "conv desc: input_nchw needs in_c*k <= 16, k <= %d, cout <= %d, stride <= 2",
-                        first_max_r(dt), FIRST_MAX_COUT);
+            return fail(DN_EUNSUPPORTED, "conv desc: input_nchw needs in_c <= 16, (in_c rounded up to 4, 8 or 16) * k <= 16, k <= %d, cout <= %d, stride <= 2",
+                        FIRST_MAX_R, FIRST_MAX_COUT);
         if (d->residual) return fail(DN_EUNSUPPORTED, "conv desc: input_nchw with residual");
     }
     const int Ho = out_side_conv(d->in_h, d->ksize, d->stride, d->pad);

@@ -65,7 +65,8 @@ def test_conv_sizes_host_arithmetic(dn):
     (dict(activation=7), "DN_EINVAL"),
     (dict(dtype=9), "DN_EINVAL"),
     (dict(input_nchw=1, in_c=64), "DN_EUNSUPPORTED"),         # C*k > 16: run does not fit
-    (dict(input_nchw=1, in_c=3, ksize=5), "DN_EUNSUPPORTED"), # 5 filter rows > 4 (BF16/FP32)
+    (dict(input_nchw=1, in_c=3, ksize=5), "DN_EUNSUPPORTED"), # 5 filter rows > 4
+    (dict(input_nchw=1, in_c=5, ksize=3), "DN_EUNSUPPORTED"), # 5 channels pad to 8: 8*3 > 16
     (dict(pool=2, residual=1), "DN_EUNSUPPORTED"),
 ])
 def test_conv_desc_validation(dn, kw, status):

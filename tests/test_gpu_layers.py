@@ -113,7 +113,10 @@ FIRST = [
     (2, 32, 32, 3, 16, 3, 1, 1, 1),     # single block / plain9 stem, pooled
     (1, 40, 72, 3, 32, 3, 1, 1, 0),     # residual stem, ragged tile edges, 2 channel blocks
     (1, 30, 34, 3, 12, 3, 2, 1, 0),     # stride 2, odd channel count
-    (2, 18, 20, 4, 48, 3, 1, 1, 1),     # 4 input channels (C*S = 12), 3 channel blocks
+    (2, 18, 20, 4, 48, 3, 1, 1, 1),     # 4 input channels, 3 channel blocks
+    (1, 21, 70, 6, 16, 2, 1, 0, 0),     # 6 channels padded to 8, 2x2 filter, ragged columns
+    (2, 17, 66, 16, 24, 1, 2, 0, 0),    # 16 channels, 1x1 stride 2
+    (1, 33, 40, 1, 64, 4, 2, 1, 0),     # 1 channel, 4x4 stride 2, 4 channel blocks
 ]
 
 
