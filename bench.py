@@ -35,6 +35,13 @@ HBM_PEAK = 8.0e12
 CSRC = os.path.join(ROOT, "paper_1811_03882_amd", "csrc")
 
 
+def _tile_desc(dn, t: int) -> str:
+    try:
+        return "%dx%d tile, %dx%d waves" % dn.tile_info(t)
+    except Exception:
+        return "direct kernel"
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("conv.hip", "dn_kernels.h"):
@@ -90,13 +97,27 @@ def time_steps(torch, fn, steps, warmup, stream):
     return wall, per
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(budget_s: float = 12.0):
-    """The FP64 oracle, as it stands, on whole 416x416 images of the 9-layer net."""
+    """The FP64 oracle, as it stands, on whole 416x416 images of the 9-layer
+    net: all OpenMP threads for about budget_s, then one image on one thread."""
+    import oracle
     import synth
     from oracle import net as onet
     net = synth.plain9()
     params = synth.make_params(net, synth.SEED_PLAIN)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
     n, t0 = 0, time.perf_counter()
     while True:
         x = synth.make_input(net, 1, synth.SEED_PLAIN, tag=100 + n)
@@ -105,9 +126,20 @@ def cpu_baseline(budget_s: float = 12.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    onet.forward(net, params, synth.make_input(net, 1, synth.SEED_PLAIN, tag=99))
+    single = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
     return {"value": n / dt, "unit": "images/s", "cores": threads, "kind": "oracle",
             "sample": "%d whole 3x416x416 images of the 9-layer net, FP64 direct convolution, "
-                      "OpenMP over (image, channel), %.1f s" % (n, dt)}
+                      "OpenMP over (image, channel), %.1f s" % (n, dt),
+            "single_thread_images_per_s": 1.0 / single, "cpu_model": _cpu_model(),
+            "host_cpus": os.cpu_count(), "cpus_available": affinity}
 
 
 def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print):
@@ -150,7 +182,7 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print)
 def traffic_from_profiles(layer_key: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     PMC summary, only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    path = os.path.join(ROOT, "profiles", "conv_dominant_b64_bf16_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -161,6 +193,70 @@ def traffic_from_profiles(layer_key: str):
         return d.get(layer_key, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError):
         return None
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(trace_csv: str, min_run: int = 20) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace CSV: per-kernel dispatch
+    statistics, and every run of >= min_run consecutive dispatches of one
+    kernel (the per-layer timing loops of this script; the first such run is
+    the dominant conv, timed right after the graph-replay steps)."""
+    rows = sorted(_csv_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    per = {}
+    for r in rows:
+        per.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| kernel | dispatches | avg us | min us | max us | total ms |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        out.append("| `%s` | %d | %.2f | %.2f | %.2f | %.3f |" % (k[:110], len(v), np.mean(v), min(v), max(v), sum(v) / 1e3))
+    runs, i = [], 0
+    while i < len(rows):
+        j = i
+        while j < len(rows) and rows[j]["Kernel_Name"] == rows[i]["Kernel_Name"]:
+            j += 1
+        if j - i >= min_run:
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[i:j]]
+            runs.append((rows[i]["Kernel_Name"], j - i, float(np.mean(d)), float(np.median(d))))
+        i = j
+    out += ["", "Runs of >= %d consecutive dispatches of one kernel (per-layer timing loops, in order):" % min_run, "",
+            "| # | kernel | dispatches | avg us | median us |", "|---|---|---|---|---|"]
+    for n, (k, c, a, m) in enumerate(runs):
+        out.append("| %d | `%s` | %d | %.2f | %.2f |" % (n, k[:110], c, a, m))
+    return "\n".join(out)
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, launches: int = 5):
+    """HBM bytes per launch of the dominant conv from two rocprofv3 --pmc runs
+    of `bench.py --pmc-driver` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
+    Each counter is scaled by what it reads for the driver's 256 MiB device
+    copy (the first copyBuffer dispatch), and the last `launches` dispatches
+    are the dominant conv."""
+    def load(path, counter):
+        disp = {}
+        for r in _csv_rows(path):
+            if r["Counter_Name"] == counter:
+                d = disp.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])
+                d[1] += float(r["Counter_Value"])
+        return [disp[k] for k in sorted(disp)]
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = load(path, counter)
+        copy = next(v for k, v in d if "copyBuffer" in k)
+        kern = d[-launches:]
+        assert len({k for k, _ in kern}) == 1, "last dispatches are not one kernel"
+        factor = copy * 1024.0 / (256 << 20)
+        res[counter] = {"copy_kib": copy, "factor": factor, "kernel": kern[0][0],
+                        "kib_per_launch": float(np.mean([v for _, v in kern])),
+                        "bytes_per_launch": float(np.mean([v for _, v in kern])) * 1024.0 / factor}
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    return {"kernel_source_hash": kernel_source_hash(),
+            "layer%d" % layer: {"kernel": res["FETCH_SIZE"]["kernel"], "hbm_bytes_per_launch": total,
+                                "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"]}}
 
 
 def main():
@@ -175,7 +271,18 @@ def main():
     ap.add_argument("--pmc-driver", action="store_true",
                     help="run only the dominant conv kernel (5 launches) and a 256 MiB device copy, "
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print a markdown summary of a rocprofv3 --kernel-trace CSV and exit (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER"),
+                    help="print the HBM-traffic JSON of two --pmc-driver counter runs and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_pmc:
+        f, w, layer = args.summarize_pmc
+        print(json.dumps(summarize_pmc(f, w, int(layer)), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: inference is data-parallel with no per-forward exchange, "
               "and this build runs on a single MI355X (see the sharding note in the design document).",
@@ -188,6 +295,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.pmc_driver:
+        # reference copy of known size first (its counters calibrate the HBM byte counts)
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     net = synth.plain9()
     params = synth.make_params(net, synth.SEED_PLAIN)
     B, H, W = 64, 416, 416
@@ -199,12 +314,6 @@ def main():
     log("[bench] building BF16 b64 net + autotune")
     nb, arena_b = build_net(dn, torch, net, dn.BF16, B, H, W, params)
     if args.pmc_driver:
-        # reference copy of known size first (its counters calibrate the HBM byte counts)
-        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
         flops = conv_flops(net, B, H, W)
         dom = max(flops, key=lambda k: flops[k][0])
         nb.forward(x, B, H, W, torch.empty((B,) + nb.output_shape(H, W), device="cuda"), stream)
@@ -222,23 +331,29 @@ def main():
     ms_step = wall * 1e3 / args.steps
     value = B * args.steps / wall
     log("[bench] bf16 b64: %.3f ms/step, %.0f images/s" % (ms_step, value))
+    # step latency over 1000 graph replays (events around each replay)
+    _, lat_b64 = time_steps(torch, fwd, 1000, 0, stream)
+    log("[bench] bf16 b64 latency over 1000 replays: p50 %.3f ms, p99 %.3f ms"
+        % (np.percentile(lat_b64, 50), np.percentile(lat_b64, 99)))
 
-    # per-conv kernel times (HIP events on the launch stream), % MFMA
+    # per-conv kernel times (HIP events on the launch stream), % MFMA; the
+    # dominant conv first, so that its launches form one run in a kernel trace
     flops = conv_flops(net, B, H, W)
+    dom = max(flops, key=lambda k: flops[k][0])  # the K = 9216 conv
+    dom_ms = nb.time_layer(dom, B, H, W, args.kernel_iters, stream)
     per_layer = {}
     for li, (fl, M, N, K) in flops.items():
-        ms = nb.time_layer(li, B, H, W, args.kernel_iters, stream)
+        ms = dom_ms if li == dom else nb.time_layer(li, B, H, W, args.kernel_iters, stream)
         plan = nb.layer_plan(li, B, H, W)
         per_layer[li] = {"ms": ms, "tflops": fl / (ms * 1e-3) / 1e12, "mfma_pct": 100.0 * fl / (ms * 1e-3) / PEAK["bf16"],
                          "M": M, "N": N, "K": K, "tile": plan["tile"], "splits": plan["splits"]}
         log("[bench]   conv layer %2d M=%6d N=%4d K=%5d tile=%d split=%d  %.4f ms  %.1f TFLOP/s  %.1f%% of BF16 peak"
             % (li, M, N, K, plan["tile"], plan["splits"], ms, per_layer[li]["tflops"], per_layer[li]["mfma_pct"]))
-    dom = max(flops, key=lambda k: flops[k][0])  # the K = 9216 conv
-    dom_ms = per_layer[dom]["ms"]
     achieved = flops[dom][0] / (dom_ms * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK["bf16"], "traffic": traffic_from_profiles("layer%d" % dom),
-                "kernel": "conv_igemm bf16, layer %d (conv3x3 1024->1024 on 13x13, M=%d N=%d K=%d)" % (dom, *flops[dom][1:]),
+                "kernel": "conv layer %d bf16, tile config %d (%s): conv3x3 1024->1024 on 13x13, M=%d N=%d K=%d"
+                          % (dom, per_layer[dom]["tile"], _tile_desc(dn, per_layer[dom]["tile"]), *flops[dom][1:]),
                 "avg_launch_ms": dom_ms}
 
     secondary = []
@@ -274,9 +389,10 @@ def main():
         y1 = torch.empty((1,) + out_shape, dtype=torch.float32, device="cuda")
         log("[bench] f32 b1 resident")
         n3, a3 = build_net(dn, torch, net, dn.F32, 1, H, W, params)
-        w3, p3 = time_steps(torch, lambda: n3.forward(x1, 1, H, W, y1, stream), 100, 10, stream)
-        secondary.append({"workload": "9-layer b1 f32 resident graph", "images_per_s": 100 / w3,
-                          "p50_ms": float(np.percentile(p3, 50)), "p99_ms": float(np.percentile(p3, 99))})
+        w3, p3 = time_steps(torch, lambda: n3.forward(x1, 1, H, W, y1, stream), 1000, 10, stream)
+        secondary.append({"workload": "9-layer b1 f32 resident graph", "images_per_s": len(p3) / w3,
+                          "p50_ms": float(np.percentile(p3, 50)), "p99_ms": float(np.percentile(p3, 99)),
+                          "replays": len(p3)})
         n3.close()
         log("[bench] f32 b1 per-layer transfer")
         n4, a4 = build_net(dn, torch, net, dn.F32, 1, H, W, params, use_graph=False, tune=False, mode=dn.PER_LAYER)
@@ -309,7 +425,8 @@ def main():
         "config": {"workload": "9-layer plain CNN (Darknet-style), batch 64, 3x416x416, BF16 MFMA / FP32 accumulate, "
                                "BN folded in FP64, hipGraph forward, autotuned tiles",
                    "global_batch": B, "image": [3, H, W], "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat_b64, 50)), "p99": float(np.percentile(lat_b64, 99)),
+                       "replays": len(lat_b64)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_conv": {str(k): v for k, v in per_layer.items()},

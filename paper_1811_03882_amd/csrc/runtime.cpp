@@ -901,7 +901,7 @@ static void load_tune_cache(dn_net *net)
     char key[256];
     int t, s;
     while (fscanf(f, "%255s %d %d", key, &t, &s) == 3)
-        if (t >= 0 && t < tile_count() && s >= 1) net->tuned[key] = {t, s};
+        if (((t >= 0 && t < tile_count()) || t == HALO_TILE) && s >= 1) net->tuned[key] = {t, s};
     fclose(f);
 }
 
