@@ -37,7 +37,7 @@ CSRC = os.path.join(ROOT, "paper_1811_03882_amd", "csrc")
 
 def _tile_desc(dn, t: int) -> str:
     try:
-        return "%dx%d tile, %dx%d waves" % dn.tile_info(t)
+        return "%dx%d tile, %dx%d waves, BF16 MFMA %d" % dn.tile_info(t)
     except Exception:
         return "direct kernel"
 

@@ -218,9 +218,14 @@ dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, f
 dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
                     float *y, void *stream);
 
-/* Number of compiled conv tile configurations and their shapes. */
+/* Number of compiled conv tile configurations and their shapes: output tile
+ * bm x bn, waves_m x waves_n waves, and the side of the MFMA blocks a BF16
+ * conv uses with it (16 or 32; other dtypes always use 16x16 blocks).  Tiles
+ * with the same block side give bitwise-identical results; 16 and 32 differ
+ * by FP32 summation order only.  Any out-pointer may be NULL; a tile outside
+ * [0, dn_tile_count()) is DN_EINVAL. */
 int dn_tile_count(void);
-dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n);
+dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n, int *mfma_bf16);
 
 const char *dn_last_error(void);
 

@@ -64,7 +64,8 @@ template <> struct Seg<FP8> {
 // ---------------------------------------------------------------- fold + pack
 // One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
 // w' = w * scale, b' = (b - mean) * scale + beta (b' = b without BN).  The
-// packed row is [k_pad] with k = (r*S + s)*cin_p + c (compact: k = r*16 + s*CP + c,
+// packed row is [k_pad] with k = (cb*R*S + r*S + s)*CB + ci, c = cb*CB + ci,
+// CB = kblock_ch(dt, cin_p, R*S) (compact: k = r*16 + s*CP + c,
 // CP = first_cp(cin)),
 // zeros in every padding.
 // FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
@@ -95,10 +96,11 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
             s = e / cp;
             c = e - s * cp;
             if (co >= cout || r >= R || s >= S || c >= cin) return 0.0;
-        } else {        // k = (r*S + s)*cin_p + c
-            const int tap = k / cin_p;
-            c = k - tap * cin_p;
-            if (co >= cout || tap >= RS || c >= cin) return 0.0;
+        } else {        // k = (cb*R*S + r*S + s)*CB + ci, c = cb*CB + ci
+            const int CB = kblock_ch(DT, cin_p, RS);
+            const int blk = k / CB, cb = blk / RS, tap = blk - cb * RS;
+            c = cb * CB + (k - blk * CB);
+            if (co >= cout || c >= cin) return 0.0;
             r = tap / S;
             s = tap - r * S;
         }

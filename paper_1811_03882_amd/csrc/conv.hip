@@ -4,7 +4,9 @@
 // K = R*S*Cin_pad):  Y[m][j] = sum_k A[m][k] * B[k][j].
 // A is never materialised: each 128-byte K-slice of an A row is gathered from
 // the NHWC input as eight 16-byte segments, each lying inside one filter tap
-// (r, s) because channels are padded to 16 bytes, and staged in LDS.  B is the
+// (r, s) because channels are padded to 16 bytes, and staged in LDS.  The K
+// order is k = (cb*R*S + r*S + s)*CB + ci (c = cb*CB + ci, CB = kblock_ch()):
+// tap-major for narrow layers, channel-block-major for wide ones.  B is the
 // packed weight matrix [cout_p][k_pad] (K contiguous).  Products run on MFMA
 // with FP32 accumulation:
 //   FP32  v_mfma_f32_16x16x4_f32        (4 issues per 16-wide K step)
@@ -25,6 +27,7 @@
 namespace dnk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
@@ -93,6 +96,27 @@ __device__ __forceinline__ int xcd_remap(int bid, int G)
     return xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
 }
 
+// Logical tile id -> (M tile, N tile).  N tiles are taken in groups of four;
+// within a group the id runs over (M tile, N tile in group), N fastest.  The
+// run of ids one XCD receives is then a block of about 8 M tiles x 4 N tiles
+// rather than 4 x 8 when N has 8 tiles, which balances the input rows and
+// weight columns its L2 has to hold.
+__device__ __forceinline__ void tile_mn(int logical, int mt, int ntn, int &mi, int &ni)
+{
+    constexpr int GN = 4;
+    const int ngf = ntn / GN;            // complete groups
+    const int gtiles = mt * GN;
+    if (logical < ngf * gtiles) {
+        const int g = logical / gtiles, r = logical - g * gtiles;
+        mi = r / GN;
+        ni = g * GN + (r - (r / GN) * GN);
+    } else {
+        const int w = ntn - ngf * GN, r = logical - ngf * gtiles;
+        mi = r / w;
+        ni = ngf * GN + (r - (r / w) * w);
+    }
+}
+
 __device__ __forceinline__ float activate(float v, int act, float slope)
 {
     return (act == 1 && !(v > 0.0f)) ? v * slope : v;
@@ -116,20 +140,24 @@ __device__ __forceinline__ u32x4 gload16(const void *base, size_t byte_off)
 // lane holds column (lane & 15) and rows 4*(lane >> 4) + i, i = 0..3; rowb /
 // colb are this lane's first row / column.  With split-K the raw FP32
 // partial sums go to the scratch plane of this split instead.
-template <int DT, int FM, int FN>
+// acc[g][f] holds rows rowb + g*RSTR + (0..3) of column colb + f*CSTR (16x16
+// blocks: RSTR = CSTR = 16; 32x32 blocks split into four row quads: RSTR = 8,
+// CSTR = 32).  Every quad starts at a multiple of 4, so with a fused pool it is
+// one 2x2 window.
+template <int DT, int FM, int FN, int RSTR = 16, int CSTR = 16>
 __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][FN], int rowb, int colb)
 {
     if (a.splits > 1) {
         float *P = a.partial + (size_t)blockIdx.z * a.M * a.cout_p;
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
-            const int col = colb + fn * 16;
+            const int col = colb + fn * CSTR;
             if (col >= a.cout_p) continue;
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int m = rowb + fm * 16 + i;
+                    const int m = rowb + fm * RSTR + i;
                     if (m < a.M) P[(size_t)m * a.cout_p + col] = acc[fm][fn][i];
                 }
         }
@@ -137,13 +165,13 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][F
     }
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
-        const int col = colb + fn * 16;
+        const int col = colb + fn * CSTR;
         if (col >= a.cout_p) continue;
         const float bias = a.bias[col];
         const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm) {
-            const int mb = rowb + fm * 16;
+            const int mb = rowb + fm * RSTR;
             if (mb >= a.M) continue;
             float v[4];
 #pragma unroll
@@ -186,7 +214,9 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 
     const int ntn = (a.cout_p + BN - 1) / BN;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int m0 = (logical / ntn) * BM, n0 = (logical % ntn) * BN;
+    int mi, ni;
+    tile_mn(logical, gridDim.x / ntn, ntn, mi, ni);
+    const int m0 = mi * BM, n0 = ni * BN;
 
     // ---- per-row gather state for A (fixed for the whole K loop)
     const int sc = tid & 7;
@@ -223,6 +253,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
     const int kt0 = blockIdx.z * a.ktiles_per_split;
     const int kt1 = min(nkt, kt0 + a.ktiles_per_split);
     const int RS = a.R * a.S;
+    const int cbsh = kblock_ch(DT, a.cin_p, RS) == a.cin_p ? -1 : 7 - (ES >> 1);  // log2 of a 128-byte block
     const u32x4 zero4 = {0u, 0u, 0u, 0u};
 
     u32x4 ra[AR], rb[BR];
@@ -238,10 +269,17 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 #define DN_GLOAD(KT)                                                                           \
     do {                                                                                       \
         const int k0_ = (KT) * BKE + sc * SEG;                                                 \
-        const int tap_ = k0_ / a.cin_p;                                                        \
-        const int c0_ = k0_ - tap_ * a.cin_p;                                                  \
+        int tap_, c0_;                                                                         \
+        if (cbsh < 0) {                                                                        \
+            tap_ = k0_ / a.cin_p;                                                              \
+            c0_ = k0_ - tap_ * a.cin_p;                                                        \
+        } else {                                                                               \
+            const int blk_ = k0_ >> cbsh, cb_ = blk_ / RS;                                     \
+            tap_ = blk_ - cb_ * RS;                                                            \
+            c0_ = (cb_ << cbsh) + (k0_ & ((1 << cbsh) - 1));                                   \
+        }                                                                                      \
         const int r_ = tap_ / a.S, s_ = tap_ - (tap_ / a.S) * a.S;                             \
-        const bool kv_ = tap_ < RS;                                                            \
+        const bool kv_ = tap_ < RS && c0_ < a.cin_p;                                           \
         _Pragma("unroll") for (int i = 0; i < AR; ++i) {                                       \
             const int hi_ = a_hi[i] + r_, wi_ = a_wi[i] + s_;                                  \
             const bool ok_ = kv_ && (unsigned)hi_ < (unsigned)a.H && (unsigned)wi_ < (unsigned)a.W; \
@@ -372,7 +410,12 @@ template <int SPR> __device__ __forceinline__ int seg_swz(int row)
     return SPR == 8 ? (row & 7) : ((row >> 2) & 3);
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR>
+// MF = 16: 16x16 MFMA blocks (every dtype); MF = 32: 32x32x16 BF16 blocks,
+// which gfx950 issues at twice the rate of 16x16x32 BF16 (same passes for
+// twice the products).  A 32x32 fragment: lane l holds row l%32 and K
+// elements [8*(l/32), 8*(l/32) + 8) of the 16-element step, i.e. one 16-byte
+// segment; the result quad q of a lane covers rows 8q + 4*(l/32) + (0..3).
+template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR, int MF = 16>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 {
     constexpr int NW = WM * WN;
@@ -383,11 +426,13 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     constexpr int AGRP = BM / RPI, BGRP = BN / RPI;     // row groups (one transfer each) per tile
     constexpr int AR = (AGRP + NW - 1) / NW, BR = (BGRP + NW - 1) / NW;  // transfers per wave (max)
     constexpr int LPT = AR + BR;
-    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / MF, FN = WTN / MF;
     constexpr int SPL = Tr<DT>::SPL;
-    constexpr int KSPT = SPR / (4 * SPL);               // MFMA K-steps per tile
-    static_assert(KSPT >= 1 && KSPT * 4 * SPL == SPR, "K-tile / MFMA step mismatch");
-    static_assert(BM % RPI == 0 && BN % RPI == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
+    constexpr int KSPT = MF == 16 ? SPR / (4 * SPL) : SPR / 2;  // MFMA K-steps per tile
+    static_assert(MF == 16 || (MF == 32 && DT == BF16), "32x32 blocks are BF16 only");
+    static_assert(KSPT >= 1 && (MF == 32 || KSPT * 4 * SPL == SPR), "K-tile / MFMA step mismatch");
+    static_assert(BM % RPI == 0 && BN % RPI == 0 && WTM % MF == 0 && WTN % MF == 0, "tile shape");
+    typedef std::conditional_t<MF == 16, f4, f16v> accT;
     static_assert(NS >= 2 && NS <= 4 && LPT * (NS - 2) < 64, "pipeline depth");
 
     __shared__ u32x4 sA[NS][BM * SPR];
@@ -397,7 +442,9 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     const int wm = wave % WM, wn = wave / WM;
     const int ntn = (a.cout_p + BN - 1) / BN;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int m0 = (logical / ntn) * BM, n0 = (logical % ntn) * BN;
+    int mi, ni;
+    tile_mn(logical, gridDim.x / ntn, ntn, mi, ni);
+    const int m0 = mi * BM, n0 = ni * BN;
     // transfers this wave issues per K-tile (waves share the row groups round-robin)
     const int my_a = (AGRP - wave + NW - 1) / NW, my_b = (BGRP - wave + NW - 1) / NW;
     const int my_lpt = my_a + my_b;
@@ -439,13 +486,22 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     const int kt0 = blockIdx.z * a.ktiles_per_split * tpk;
     const int kt1 = min(nkt, kt0 + a.ktiles_per_split * tpk);
     const int RS = a.R * a.S;
+    // channel-block-major K order uses a power-of-two block (32 / 64 / 128 channels)
+    const int cbsh = kblock_ch(DT, a.cin_p, RS) == a.cin_p ? -1 : 7 - (ES >> 1);
 
     auto issue = [&](int kt, int st) {
         const int k0 = kt * BKE + sc * SEG;
-        const int tap = k0 / a.cin_p;
-        const int c0 = k0 - tap * a.cin_p;
+        int tap, c0;
+        if (cbsh < 0) {
+            tap = k0 / a.cin_p;
+            c0 = k0 - tap * a.cin_p;
+        } else {
+            const int blk = k0 >> cbsh, cb = blk / RS;
+            tap = blk - cb * RS;
+            c0 = (cb << cbsh) + (k0 & ((1 << cbsh) - 1));
+        }
         const int r = tap / a.S, s = tap - (tap / a.S) * a.S;
-        const bool kv = tap < RS;
+        const bool kv = tap < RS && c0 < a.cin_p;
 #pragma unroll
         for (int i = 0; i < AR; ++i) {
             if (AGRP % NW != 0 && i == AR - 1 && i >= my_a) break;  // wave-uniform
@@ -463,11 +519,11 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
         }
     };
 
-    f4 acc[FM][FN];
+    accT acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FN; ++j) acc[i][j] = accT{};
     const int lrow = lane & 15, lgrp = lane >> 4;
 
 #pragma unroll
@@ -484,6 +540,31 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
         else { if (after >= 2) wait_vm<(LPT > 1 ? LPT - 2 : 0) * 2>(); else wait_vm<(LPT > 1 ? LPT - 2 : 0)>(); }
         lds_barrier();  // every wave's transfers landed; every wave is done with tile kt-1
         if (kt + NS - 1 < kt1) issue(kt + NS - 1, cs == 0 ? NS - 1 : cs - 1);
+        if constexpr (MF == 32) {
+            const int r32 = lane & 31, h = lane >> 5;
+#pragma unroll
+            for (int ks = 0; ks < KSPT; ++ks) {
+                const int seg = ks * 2 + h;
+                u32x4 af[FM], bfr[FN];
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm) {
+                    const int row = wm * WTM + fm * 32 + r32;
+                    af[fm] = sA[cs][row * SPR + (seg ^ seg_swz<SPR>(row))];
+                }
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) {
+                    const int row = wn * WTN + fn * 32 + r32;
+                    bfr[fn] = sB[cs][row * SPR + (seg ^ seg_swz<SPR>(row))];
+                }
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                    for (int fn = 0; fn < FN; ++fn)
+                        acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[fm]),
+                                                                             __builtin_bit_cast(bf16x8, bfr[fn]),
+                                                                             acc[fm][fn], 0, 0, 0);
+            }
+        } else {
 #pragma unroll
         for (int ks = 0; ks < KSPT; ++ks) {
             u32x4 af[FM][SPL], bfr[FN][SPL];
@@ -510,9 +591,22 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn) mma<DT>(acc[fm][fn], af[fm], bfr[fn]);
         }
+        }
         cs = cs + 1 == NS ? 0 : cs + 1;
     }
-    conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
+    if constexpr (MF == 32) {
+        f4 q4[FM * 4][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn)
+                    q4[fm * 4 + q][fn] = f4{acc[fm][fn][4 * q], acc[fm][fn][4 * q + 1], acc[fm][fn][4 * q + 2], acc[fm][fn][4 * q + 3]};
+        conv_epilogue<DT, FM * 4, FN, 8, 32>(a, q4, m0 + wm * WTM + 4 * (lane >> 5), n0 + wn * WTN + (lane & 31));
+    } else {
+        conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
+    }
 }
 
 // Split-K finish: sum the partials in split order, then the same epilogue.
@@ -696,6 +790,18 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
             }
     __syncthreads();
 
+    // per-lane epilogue constants: channels nb*16 + 4*lgrp + i (loaded once, not per block)
+    float bias4[MAXNB][4], scl4[MAXNB][4];
+#pragma unroll
+    for (int nb = 0; nb < MAXNB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ch = nb * 16 + 4 * lgrp + i;
+            const bool live = nb < nb_count && ch < a.cout_p;
+            bias4[nb][i] = live ? a.bias[ch] : 0.0f;
+            scl4[nb][i] = (DT == FP8 && live) ? a.wscale[ch] * a.in_scale : 1.0f;
+        }
+
     const int blocks = a.th * FT_W / 16;  // 16-pixel MFMA blocks per tile
     for (int b = wave; b < blocks; b += 4) {
         // this lane's pixel (B column) in the tile
@@ -742,11 +848,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
             const bool live = ch0 < a.cout_p;  // cout_p is a multiple of 4
             float v[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float bias = live ? a.bias[ch0 + i] : 0.0f;
-                const float scl = (DT == FP8 && live) ? a.wscale[ch0 + i] * a.in_scale : 1.0f;
-                v[i] = activate(acc[i] * scl + bias, a.act, a.slope) * a.out_inv_scale;
-            }
+            for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl4[nb][i] + bias4[nb][i], a.act, a.slope) * a.out_inv_scale;
             if (POOL) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = quad_max<0x4E>(quad_max<0xB1>(v[i]));
@@ -846,7 +948,7 @@ constexpr int HALO_LDS_MAX = 96 * 1024;
 
 bool halo_ok(int dt, const ConvArgs &a)
 {
-    return a.R * a.S * a.cin_p * esize(dt) <= HALO_KMAX_BYTES && a.cout_p <= 64 && a.stride <= 2 &&
+    return kblock_ch(dt, a.cin_p, a.R * a.S) == a.cin_p && a.R * a.S * a.cin_p * esize(dt) <= HALO_KMAX_BYTES && a.cout_p <= 64 && a.stride <= 2 &&
            halo_lds_bytes(dt, a, 8) <= HALO_LDS_MAX;
 }
 
@@ -1074,6 +1176,20 @@ static const TileCfg kTiles[] = {
     {352, 128, 2, 2},  // 24: 2 stages, 4 waves
     {352, 128, 2, 8},  // 25: 2 stages, 16 waves (4 per SIMD)
     {256, 256, 2, 8},  // 26: 2 stages, 16 waves
+    // 32x32x16 BF16 blocks (other dtypes run the same tile with 16x16 blocks)
+    {384, 128, 4, 2, 32},  // 27: 29 x 8 = 232 tiles for M = 64*169; 2 stages, 8 waves of 96x64
+    {384, 128, 4, 4, 32},  // 28: 2 stages, 16 waves of 96x32
+    {256, 256, 2, 4, 32},  // 29: 2 stages, 8 waves of 128x64
+    {256, 256, 4, 4, 32},  // 30: 2 stages, 16 waves of 64x64
+    {256, 128, 4, 2, 32},  // 31: 3 stages, 8 waves of 64x64
+    {128, 128, 2, 2, 32},  // 32: 4 stages, 4 waves of 64x64
+    {352, 128, 11, 1, 32}, // 33: 2 stages, 11 waves of 32x128
+    // 64-byte K-tiles, 4 stages (three K-tiles in flight)
+    {352, 128, 2, 8},      // 34: 16 waves
+    {384, 128, 4, 2, 32},  // 35: 8 waves of 96x64
+    {384, 128, 4, 4, 32},  // 36: 16 waves of 96x32
+    {256, 256, 4, 4, 32},  // 37: 16 waves of 64x64
+    {352, 128, 11, 1, 32}, // 38: 11 waves of 32x128
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -1088,23 +1204,27 @@ static hipError_t go(const ConvArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR = 8>
+template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR = 8, int MF = 16>
 static hipError_t go_dl(ConvArgs a, hipStream_t s)
 {
-    // buffer offsets are 32-bit: the LDS-DMA kernels need tensors below 2 GiB
-    const size_t xb = (size_t)a.batch * a.H * a.W * a.cin_p * esize(DT);
-    const size_t wb = (size_t)a.cout_p * a.k_pad * esize(DT);
-    if (xb >= DN_OOB || wb >= DN_OOB) return go<DT, 128, 128, 2, 2>(a, s);  // register-staged path
-    a.x_bytes = (unsigned)xb;
-    a.w_bytes = (unsigned)wb;
-    const int mt = (a.M + BM - 1) / BM, nt = (a.cout_p + BN - 1) / BN;
-    dim3 grid(mt * nt, 1, a.splits);
-    if constexpr (DT == FP8 && SPR == 4) {
-        return go_dl<DT, BM, BN, WM, WN, NS == 4 ? 2 : NS, 8>(a, s);  // FP8 K-steps need 128-byte tiles
+    if constexpr (MF == 32 && DT != BF16) {
+        return go_dl<DT, BM, BN, WM, WN, NS, SPR, 16>(a, s);  // 32x32 blocks: BF16 only
     } else {
-        hipLaunchKernelGGL((conv_igemm_dl<DT, BM, BN, WM, WN, NS, SPR>), grid, dim3(64 * WM * WN), 0, s, a);
+        // buffer offsets are 32-bit: the LDS-DMA kernels need tensors below 2 GiB
+        const size_t xb = (size_t)a.batch * a.H * a.W * a.cin_p * esize(DT);
+        const size_t wb = (size_t)a.cout_p * a.k_pad * esize(DT);
+        if (xb >= DN_OOB || wb >= DN_OOB) return go<DT, 128, 128, 2, 2>(a, s);  // register-staged path
+        a.x_bytes = (unsigned)xb;
+        a.w_bytes = (unsigned)wb;
+        const int mt = (a.M + BM - 1) / BM, nt = (a.cout_p + BN - 1) / BN;
+        dim3 grid(mt * nt, 1, a.splits);
+        if constexpr (DT == FP8 && SPR == 4) {
+            return go_dl<DT, BM, BN, WM, WN, NS == 4 ? 2 : NS, 8, MF>(a, s);  // FP8 K-steps need 128-byte tiles
+        } else {
+            hipLaunchKernelGGL((conv_igemm_dl<DT, BM, BN, WM, WN, NS, SPR, MF>), grid, dim3(64 * WM * WN), 0, s, a);
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
 }
 
 template <int DT>
@@ -1138,6 +1258,18 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 24: return go_dl<DT, 352, 128, 2, 2, 2>(a, s);
     case 25: return go_dl<DT, 352, 128, 2, 8, 2>(a, s);
     case 26: return go_dl<DT, 256, 256, 2, 8, 2>(a, s);
+    case 27: return go_dl<DT, 384, 128, 4, 2, 2, 8, 32>(a, s);
+    case 28: return go_dl<DT, 384, 128, 4, 4, 2, 8, 32>(a, s);
+    case 29: return go_dl<DT, 256, 256, 2, 4, 2, 8, 32>(a, s);
+    case 30: return go_dl<DT, 256, 256, 4, 4, 2, 8, 32>(a, s);
+    case 31: return go_dl<DT, 256, 128, 4, 2, 3, 8, 32>(a, s);
+    case 32: return go_dl<DT, 128, 128, 2, 2, 4, 8, 32>(a, s);
+    case 33: return go_dl<DT, 352, 128, 11, 1, 2, 8, 32>(a, s);
+    case 34: return go_dl<DT, 352, 128, 2, 8, 4, 4>(a, s);
+    case 35: return go_dl<DT, 384, 128, 4, 2, 4, 4, 32>(a, s);
+    case 36: return go_dl<DT, 384, 128, 4, 4, 4, 4, 32>(a, s);
+    case 37: return go_dl<DT, 256, 256, 4, 4, 4, 4, 32>(a, s);
+    case 38: return go_dl<DT, 352, 128, 11, 1, 4, 4, 32>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

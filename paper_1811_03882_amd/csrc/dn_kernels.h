@@ -18,6 +18,16 @@ __host__ __device__ constexpr int seg_el(int dt) { return 16 / esize(dt); }
 __host__ __device__ constexpr int cpad(int dt, int c) { return (c + seg_el(dt) - 1) / seg_el(dt) * seg_el(dt); }
 // K-tile of the implicit GEMM: 128 bytes of one A/B row (8 segments).
 __host__ __device__ constexpr int bk_el(int dt) { return 128 / esize(dt); }
+// Channels per K block of a packed weight row: k = (cb*R*S + r*S + s)*CB + ci
+// with input channel c = cb*CB + ci.  When a layer's padded channels span
+// more than one 128-byte K-tile and it has more than one tap, CB is one
+// 128-byte block: every tap of one channel block comes before the next block,
+// so the taps' re-reads of the same input pixels follow each other closely
+// (L2 hits).  Otherwise CB = cin_p, the tap-major order k = (r*S + s)*cin_p + c.
+__host__ __device__ constexpr int kblock_ch(int dt, int cin_p, int RS)
+{
+    return (RS > 1 && cin_p * esize(dt) > 128 && (cin_p * esize(dt)) % 128 == 0) ? 128 / esize(dt) : cin_p;
+}
 
 // Arguments of one implicit-GEMM convolution launch.
 //   A[m][k] = x[n][ho*st - pad + r][wo*st - pad + s][c],  k = (r*S + s)*cin_p + c
@@ -77,7 +87,7 @@ constexpr int HALO_TILE = 100;
 bool halo_ok(int dt, const ConvArgs &a);
 hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s);
 
-struct TileCfg { int bm, bn, wm, wn; };
+struct TileCfg { int bm, bn, wm, wn, mf; };  // mf: MFMA block side for BF16 (0 = 16)
 
 int tile_count();
 TileCfg tile_cfg(int i);

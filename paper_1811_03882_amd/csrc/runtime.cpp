@@ -1241,7 +1241,7 @@ extern "C" dn_status dn_egress(int dtype, int batch, int c, int h, int w, const 
 
 extern "C" int dn_tile_count(void) { return tile_count(); }
 
-extern "C" dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n)
+extern "C" dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int *waves_n, int *mfma_bf16)
 {
     if (tile < 0 || tile >= tile_count()) return fail(DN_EINVAL, "tile %d out of range", tile);
     const TileCfg t = tile_cfg(tile);
@@ -1249,5 +1249,6 @@ extern "C" dn_status dn_tile_info(int tile, int *bm, int *bn, int *waves_m, int 
     if (bn) *bn = t.bn;
     if (waves_m) *waves_m = t.wm;
     if (waves_n) *waves_n = t.wn;
+    if (mfma_bf16) *mfma_bf16 = t.mf ? t.mf : 16;
     return DN_OK;
 }

@@ -84,7 +84,7 @@ SIGNATURES = {
     "dn_ingest": (_i, [_i, _i, _i, _i, _i, _vp, _f, _vp, _vp]),
     "dn_egress": (_i, [_i, _i, _i, _i, _i, _vp, _f, _vp, _vp]),
     "dn_tile_count": (_i, []),
-    "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip]),
+    "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip, _ip]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -159,8 +159,9 @@ def tile_count() -> int:
     return LIB.dn_tile_count()
 
 
-def tile_info(t: int) -> Tuple[int, int, int, int]:
-    v = [_i() for _ in range(4)]
+def tile_info(t: int) -> Tuple[int, int, int, int, int]:
+    """(bm, bn, waves_m, waves_n, BF16 MFMA block side) of tile config t."""
+    v = [_i() for _ in range(5)]
     check(LIB.dn_tile_info(t, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
 

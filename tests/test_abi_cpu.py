@@ -41,7 +41,8 @@ def test_channel_pad_and_tiles(dn):
     assert dn.channel_pad(7, 3) == -1
     assert dn.tile_count() >= 10
     for t in range(dn.tile_count()):
-        bm, bn, wm, wn = dn.tile_info(t)
+        bm, bn, wm, wn, mf = dn.tile_info(t)
+        assert mf in (16, 32) and bm % (wm * mf) == 0 and bn % (wn * mf) == 0
         assert bm % (16 * wm) == 0 and bn % (16 * wn) == 0
     with pytest.raises(dn.DnError) as e:
         dn.tile_info(dn.tile_count())

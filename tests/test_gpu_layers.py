@@ -88,7 +88,9 @@ SHAPES = [
     (1, 13, 13, 64, 128, 3, 1, 1, 0, 1, True),   # M = 169 (13x13), ragged tail
     (3, 9, 11, 32, 125, 1, 1, 0, 0, 0, False),   # 1x1 linear, Cout 125 (padded)
     (2, 16, 16, 48, 64, 3, 2, 1, 0, 1, True),    # stride 2
-    (1, 8, 8, 256, 96, 3, 1, 1, 0, 1, True),     # long K
+    (1, 8, 8, 256, 96, 3, 1, 1, 0, 1, True),     # long K, channel-block-major K order
+    (1, 10, 12, 96, 40, 3, 1, 1, 0, 1, True),    # 3 FP32 channel blocks; BF16 / FP8 tap-major
+    (2, 7, 9, 320, 64, 2, 1, 0, 0, 1, True),     # 2x2 filter, 5 BF16 / 10 FP32 channel blocks
 ]
 
 
@@ -191,8 +193,14 @@ def test_every_tile_config_agrees(dn, dtype):
         assert err < G.GATE[dtype]
         outs.append(got)
     # the K-reduction order does not depend on the tile shape: identical bits
-    for o in outs[1:]:
-        np.testing.assert_array_equal(o, outs[0])
+    # among tiles with the same MFMA block (BF16 32x32 blocks sum each 16-wide
+    # K step in one instruction, 16x16 blocks each 32-wide step: FP32 rounding
+    # differs, so across block sides only the storage rounding may differ)
+    side = [dn.tile_info(t)[4] if dtype == dn.BF16 else 16 for t in range(dn.tile_count())]
+    for t, o in enumerate(outs):
+        first = side.index(side[t])
+        np.testing.assert_array_equal(o, outs[first])
+        assert G.rel_l2(o, outs[0]) < 1e-3
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
@@ -220,6 +228,30 @@ def test_conv_with_fused_residual(dn, dtype):
         kw = dict(in_scale=G.fp8_scale(x), res_scale=G.fp8_scale(r), out_scale=G.fp8_scale(ref))
     got = G.run_conv(dn, dtype, x, p, 3, 1, 1, 1, res=r, **kw)
     assert G.rel_l2(got, ref) < G.GATE[dtype]
+
+
+def test_bf16_32x32_tiles_pool_residual_split(dn):
+    """Every BF16 tile with 32x32 MFMA blocks, with the fused pool, the fused
+    residual and split-K, against the oracle and against a 16x16 tile."""
+    tiles = [t for t in range(dn.tile_count()) if dn.tile_info(t)[4] == 32]
+    assert tiles
+    b, h, w, cin, cout = 2, 14, 18, 72, 96
+    p = _params(cout, cin, 3, 17)
+    x = synth.make_tensor((b, cin, h, w), 14, 0, 0.0, 1.0)
+    r = synth.make_tensor((b, cout, h, w), 14, 1, -1.0, 1.0)
+    ref_pool = _oracle_conv(x, p, 3, 1, 1, 1, pool=True)
+    ref_res = _oracle_conv(x, p, 3, 1, 1, 1, res=r)
+    base_pool = G.run_conv(dn, dn.BF16, x, p, 3, 1, 1, 1, pool=1, tile=0, splits=1)
+    for t in tiles:
+        got = G.run_conv(dn, dn.BF16, x, p, 3, 1, 1, 1, pool=1, tile=t, splits=1)
+        e1 = G.rel_l2(got, ref_pool)
+        got_r = G.run_conv(dn, dn.BF16, x, p, 3, 1, 1, 1, res=r, tile=t, splits=1)
+        e2 = G.rel_l2(got_r, ref_res)
+        got_s = G.run_conv(dn, dn.BF16, x, p, 3, 1, 1, 1, res=r, tile=t, splits=3)
+        e3 = G.rel_l2(got_s, ref_res)
+        print("tile %d %s pool %.3e residual %.3e split3 %.3e" % (t, dn.tile_info(t), e1, e2, e3))
+        assert max(e1, e2, e3) < G.GATE[dn.BF16]
+        assert G.rel_l2(got, base_pool) < 1e-3
 
 
 # ---------------------------------------------------------------- pool / add
