@@ -117,9 +117,13 @@ __device__ __forceinline__ void tile_mn(int logical, int mt, int ntn, int &mi, i
     }
 }
 
+// Leaky: v for v > 0, else v * slope.  For 0 <= slope <= 1 that is exactly
+// max(v, v * slope) (signed zeros and NaN included), two instructions.
 __device__ __forceinline__ float activate(float v, int act, float slope)
 {
-    return (act == 1 && !(v > 0.0f)) ? v * slope : v;
+    if (act != 1) return v;
+    if (slope >= 0.0f && slope <= 1.0f) return fmaxf(v, v * slope);
+    return v > 0.0f ? v : v * slope;
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -704,12 +708,6 @@ template <int DT> __device__ __forceinline__ void store4(void *y, size_t idx, co
     }
 }
 
-// max with the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (0x4E) of its quad
-template <int CTRL> __device__ __forceinline__ float quad_max(float v)
-{
-    return fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false)));
-}
-
 template <int DT, bool POOL, int CP>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 {
@@ -723,7 +721,8 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     constexpr int MAXNB = FIRST_MAX_COUT / 16;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int LH = (a.th - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lrow = lane & 15, lgrp = lane >> 4;
     const int n = blockIdx.z;
     const int th0 = blockIdx.y * a.th, tw0 = blockIdx.x * FT_W;
@@ -759,6 +758,10 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
         }
     }
 
+    // 16 zero bytes after the window: read units past row R or tap S read here
+    const int zaddr = (LH * LW * PIXB + 15) & ~15;
+    if (tid == 0) *reinterpret_cast<u32x4 *>(lds_raw + zaddr) = u32x4{0u, 0u, 0u, 0u};
+
     // ---- this lane's window offsets (bytes, relative to its pixel) for every
     // read unit of its K segments; -1 where the unit lies past row R or tap S
     int uoff[MAXKS][SPL][UPS];
@@ -790,31 +793,56 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
             }
     __syncthreads();
 
-    // per-lane epilogue constants: channels nb*16 + 4*lgrp + i (loaded once, not per block)
+    // per-lane epilogue constants, loaded once.  POOL: pixels are MFMA operand A,
+    // so a lane holds one channel (nb*16 + lrow) of the four pixels of one 2x2
+    // window and pools in registers.  Otherwise: weights are operand A and a
+    // lane holds channels nb*16 + 4*lgrp + (0..3) of one pixel.  The output
+    // scale (1 except FP8) folds into scale and bias for BF16 / FP32.
+    const float ofold = DT == FP8 ? 1.0f : a.out_inv_scale;
     float bias4[MAXNB][4], scl4[MAXNB][4];
 #pragma unroll
     for (int nb = 0; nb < MAXNB; ++nb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int ch = nb * 16 + 4 * lgrp + i;
+            const int ch = POOL ? nb * 16 + lrow : nb * 16 + 4 * lgrp + i;
             const bool live = nb < nb_count && ch < a.cout_p;
-            bias4[nb][i] = live ? a.bias[ch] : 0.0f;
-            scl4[nb][i] = (DT == FP8 && live) ? a.wscale[ch] * a.in_scale : 1.0f;
+            bias4[nb][i] = live ? a.bias[ch] * ofold : 0.0f;
+            scl4[nb][i] = (DT == FP8 && live) ? a.wscale[ch] * a.in_scale : ofold;
         }
+    const float opost = DT == FP8 ? a.out_inv_scale : 1.0f;
+    // this image's output; offsets inside one image fit in 32 bits (checked at launch)
+    const int Hy = POOL ? a.Ho >> 1 : a.Ho, Wy = POOL ? a.Wo >> 1 : a.Wo;
+    unsigned char *yimg = reinterpret_cast<unsigned char *>(a.y) + (size_t)n * Hy * Wy * a.cout_p * ES;
+    // the lane's part of its pixel position; the block's part is wave-uniform
+    int lho, lwo;
+    if (POOL) {
+        lho = (lrow & 3) >> 1;
+        lwo = 2 * (lrow >> 2) + (lrow & 1);
+    } else {
+        lho = 0;
+        lwo = lrow;
+    }
+    const int lpx = (lho * LW + lwo) * a.stride * PIXB;
+    int uaddr[MAXKS][SPL][UPS];  // lane pixel + unit offset, or the zero area (flagged by -1 - zaddr)
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks)
+#pragma unroll
+        for (int j = 0; j < SPL; ++j)
+#pragma unroll
+            for (int u = 0; u < UPS; ++u) uaddr[ks][j][u] = uoff[ks][j][u] >= 0 ? lpx + uoff[ks][j][u] : -1;
 
     const int blocks = a.th * FT_W / 16;  // 16-pixel MFMA blocks per tile
     for (int b = wave; b < blocks; b += 4) {
-        // this lane's pixel (B column) in the tile
-        int ho_l, wo_l;
+        // wave-uniform part of the block's pixel positions
+        int bho, bwo;
         if (POOL) {
-            const int rp = b / (FT_W / 8), wg = b % (FT_W / 8), q = lrow & 3;
-            ho_l = 2 * rp + (q >> 1);
-            wo_l = 2 * (wg * 4 + (lrow >> 2)) + (q & 1);
+            bho = 2 * (b / (FT_W / 8));
+            bwo = 8 * (b % (FT_W / 8));
         } else {
-            ho_l = b / (FT_W / 16);
-            wo_l = (b % (FT_W / 16)) * 16 + lrow;
+            bho = b / (FT_W / 16);
+            bwo = (b % (FT_W / 16)) * 16;
         }
-        const unsigned char *px = lds_raw + (size_t)(ho_l * a.stride * LW + wo_l * a.stride) * PIXB;
+        const int bpx = (bho * LW + bwo) * a.stride * PIXB;
         u32x4 bf[MAXKS][SPL];
 #pragma unroll
         for (int ks = 0; ks < MAXKS; ++ks)
@@ -823,43 +851,46 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 unsigned wv[4];
 #pragma unroll
                 for (int u = 0; u < UPS; ++u) {
-                    const int o = uoff[ks][j][u];
+                    const int ua = uaddr[ks][j][u];
+                    const unsigned char *src = lds_raw + (ua >= 0 ? bpx + ua : zaddr);
                     if constexpr (UB == 16) {
-                        const u32x4 t = o >= 0 ? *reinterpret_cast<const u32x4 *>(px + o) : u32x4{0u, 0u, 0u, 0u};
+                        const u32x4 t = *reinterpret_cast<const u32x4 *>(src);
                         wv[0] = t.x; wv[1] = t.y; wv[2] = t.z; wv[3] = t.w;
                     } else if constexpr (UB == 8) {
-                        const uint2 t = o >= 0 ? *reinterpret_cast<const uint2 *>(px + o) : make_uint2(0u, 0u);
+                        const uint2 t = *reinterpret_cast<const uint2 *>(src);
                         wv[2 * u] = t.x; wv[2 * u + 1] = t.y;
                     } else {
-                        wv[u] = o >= 0 ? *reinterpret_cast<const unsigned *>(px + o) : 0u;
+                        wv[u] = *reinterpret_cast<const unsigned *>(src);
                     }
                 }
                 bf[ks][j] = u32x4{wv[0], wv[1], wv[2], wv[3]};
             }
+        // K steps past k_pad multiply zero weights by zero data: no branches
 #pragma unroll
         for (int nb = 0; nb < MAXNB; ++nb) {
             if (nb >= nb_count) break;
             f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < MAXKS; ++ks)
-                if (ks < KS) mma<DT>(acc, aw[nb][ks], bf[ks]);
-            // acc[i]: channel ch0 + i of this lane's pixel
-            const int ch0 = nb * 16 + 4 * lgrp;
-            const bool live = ch0 < a.cout_p;  // cout_p is a multiple of 4
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl4[nb][i] + bias4[nb][i], a.act, a.slope) * a.out_inv_scale;
             if (POOL) {
+                // acc[i]: channel nb*16 + lrow of pixel 4*lgrp + i = quadrant i of window lgrp.
+                // The max is taken on the accumulators: scale > 0, bias, activation
+                // and rounding are monotone, so this equals pooling the outputs.
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = quad_max<0x4E>(quad_max<0xB1>(v[i]));
-                const int rp = b / (FT_W / 8), wg = b % (FT_W / 8);
-                const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + (lrow >> 2);
-                if (live && (lrow & 3) == 0 && hp < (a.Ho >> 1) && wp < (a.Wo >> 1))
-                    store4<DT>(a.y, (((size_t)n * (a.Ho >> 1) + hp) * (a.Wo >> 1) + wp) * a.cout_p + ch0, v);
+                for (int ks = 0; ks < MAXKS; ++ks) mma<DT>(acc, bf[ks], aw[nb][ks]);
+                const int col = nb * 16 + lrow;
+                const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+                const float o = activate(mx * scl4[nb][0] + bias4[nb][0], a.act, a.slope) * opost;
+                const int hp = (th0 >> 1) + (bho >> 1), wp = (tw0 >> 1) + (bwo >> 1) + lgrp;
+                if (hp < Hy && col < a.cout_p && wp < Wy) store_el<DT>(yimg, (hp * Wy + wp) * a.cout_p + col, o);
             } else {
-                const int ho = th0 + ho_l, wo = tw0 + wo_l;
-                if (live && ho < a.Ho && wo < a.Wo)
-                    store4<DT>(a.y, (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + ch0, v);
+                // acc[i]: channel ch0 + i of this lane's pixel
+#pragma unroll
+                for (int ks = 0; ks < MAXKS; ++ks) mma<DT>(acc, aw[nb][ks], bf[ks]);
+                const int ch0 = nb * 16 + 4 * lgrp;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl4[nb][i] + bias4[nb][i], a.act, a.slope) * opost;
+                const int ho = th0 + bho, wo = tw0 + bwo + lrow;
+                if (ho < a.Ho && ch0 < a.cout_p && wo < a.Wo) store4<DT>(yimg, (ho * a.Wo + wo) * a.cout_p + ch0, v);
             }
         }
     }
@@ -868,7 +899,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 static size_t first_lds_for(int C, int R, int S, int stride, int th, int dt)
 {
     const int LH = (th - 1) * stride + R, LW = (FT_W - 1) * stride + S;
-    return (size_t)LH * LW * first_cp(C) * esize(dt);
+    return (((size_t)LH * LW * first_cp(C) * esize(dt) + 15) & ~(size_t)15) + 16;  // window + 16 zero bytes
 }
 static int first_tile_h(int dt, int C, int R, int S, int stride)
 {
@@ -885,7 +916,7 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     b.th = first_tile_h(dt, a.C, a.R, a.S, a.stride);
     const size_t lds = first_lds_for(a.C, a.R, a.S, a.stride, b.th, dt);
     if (lds > FIRST_LDS_MAX || a.R > FIRST_MAX_R || a.C > 16 || first_cp(a.C) * a.S > 16 || a.cout_p > FIRST_MAX_COUT ||
-        a.stride > 2 || (a.cout_p & 3))
+        a.stride > 2 || (a.cout_p & 3) || (size_t)a.Ho * a.Wo * a.cout_p >= (1u << 31))
         return hipErrorInvalidValue;
     dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + b.th - 1) / b.th, a.batch);
 #define DN_FIRST_CP(D, P, C)                                                                         \
