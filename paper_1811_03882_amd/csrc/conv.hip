@@ -177,14 +177,16 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][F
         for (int fm = 0; fm < FM; ++fm) {
             const int mb = rowb + fm * RSTR;
             if (mb >= a.M) continue;
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = activate(acc[fm][fn][i] * scl + bias, a.act, a.slope);
             if (a.pool) {
-                // rows mb..mb+3 are one 2x2 window (M is a multiple of 4 here)
-                const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
-                store_el<DT>(a.y, (size_t)(mb >> 2) * a.cout_p + col, mx * a.out_inv_scale);
+                // rows mb..mb+3 are one 2x2 window (M is a multiple of 4 here); pooling
+                // the accumulators is exact: scale > 0, and bias, activation and
+                // rounding are monotone
+                const float mx = fmaxf(fmaxf(acc[fm][fn][0], acc[fm][fn][1]), fmaxf(acc[fm][fn][2], acc[fm][fn][3]));
+                store_el<DT>(a.y, (size_t)(mb >> 2) * a.cout_p + col, activate(mx * scl + bias, a.act, a.slope) * a.out_inv_scale);
             } else {
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = activate(acc[fm][fn][i] * scl + bias, a.act, a.slope);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int m = mb + i;
@@ -972,7 +974,7 @@ int halo_lds_bytes(int dt, const ConvArgs &a, int th)
     const int wch = ku * ES / 16, wst = wch | 1;
     const int lh = (th - 1) * a.stride + a.R, lw = (HT_W - 1) * a.stride + a.S;
     const int coutp = (a.cout_p + 15) / 16 * 16;
-    return (lh * lw * pst + coutp * wst) * 16;
+    return (lh * lw * pst + coutp * wst + 1) * 16;  // window, weights, one zero chunk
 }
 
 constexpr int HALO_LDS_MAX = 96 * 1024;
@@ -997,7 +999,8 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     extern __shared__ __align__(16) unsigned char halo_raw[];
     u32x4 *win = reinterpret_cast<u32x4 *>(halo_raw);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lrow = lane & 15, lgrp = lane >> 4;
     const int n = blockIdx.z, th0 = blockIdx.y * TH, tw0 = blockIdx.x * HT_W;
     const int K = a.R * a.S * a.cin_p;
@@ -1008,6 +1011,8 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     u32x4 *wlds = win + LH * LW * pst;
     constexpr int nb_count = NB;
     const u32x4 z4 = {0u, 0u, 0u, 0u};
+    const int zchunk = LH * LW * pst + NB * 16 * wst;  // reads past K land on this zero chunk
+    if (tid == 0) win[zchunk] = z4;
 
     // ---- input window -> LDS (8 loads in flight per thread)
     {
@@ -1093,7 +1098,7 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
         for (int i = 0; i < NBW; ++i) {
             u32x4 af[SPL];
 #pragma unroll
-            for (int j = 0; j < SPL; ++j) af[j] = toff[j] >= 0 ? win[pbase[i] + toff[j]] : z4;
+            for (int j = 0; j < SPL; ++j) af[j] = win[toff[j] >= 0 ? pbase[i] + toff[j] : zchunk];
 #pragma unroll
             for (int nb = 0; nb < MAXNB; ++nb)
                 if (nb < nb_count) mma<DT>(acc[i][nb], af, bfr[nb]);
@@ -1112,17 +1117,18 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
             const int b = wave + 4 * i;
-            float v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = activate(acc[i][nb][q] * scl + bias, a.act, a.slope);
             if (POOL) {
+                // a lane's four rows are one 2x2 window: pool the accumulators
+                // (scale > 0; bias, activation and rounding are monotone)
+                const float mx = fmaxf(fmaxf(acc[i][nb][0], acc[i][nb][1]), fmaxf(acc[i][nb][2], acc[i][nb][3]));
+                const float o = activate(mx * scl + bias, a.act, a.slope) * a.out_inv_scale;
                 const int rp = b / (HT_W / 8), wg = b % (HT_W / 8);
                 const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
-                if (hp < Hp && wp < Wp) {
-                    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
-                    store_el<DT>(a.y, (((size_t)n * Hp + hp) * Wp + wp) * a.cout_p + col, mx * a.out_inv_scale);
-                }
+                if (hp < Hp && wp < Wp) store_el<DT>(a.y, (((size_t)n * Hp + hp) * Wp + wp) * a.cout_p + col, o);
             } else {
+                float v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = activate(acc[i][nb][q] * scl + bias, a.act, a.slope);
                 const int ho = th0 + b / (HT_W / 16);
                 if (ho < a.Ho) {
 #pragma unroll
