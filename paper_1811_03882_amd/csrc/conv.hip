@@ -1169,7 +1169,8 @@ static hipError_t go_halo_dt(const ConvArgs &a, int th, dim3 grid, size_t lds, h
 hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s)
 {
     if (!halo_ok(dt, a)) return hipErrorInvalidValue;
-    const int th = halo_lds_bytes(dt, a, 16) <= HALO_LDS_MAX ? 16 : 8;
+    // 16-row tiles when two workgroups still fit in a CU's LDS, else 8 rows
+    const int th = halo_lds_bytes(dt, a, 16) <= 80 * 1024 ? 16 : 8;
     dim3 grid((a.Wo + HT_W - 1) / HT_W, (a.Ho + th - 1) / th, a.batch);
     const size_t lds = halo_lds_bytes(dt, a, th);
     switch (dt) {
@@ -1227,6 +1228,12 @@ static const TileCfg kTiles[] = {
     {384, 128, 4, 4, 32},  // 36: 16 waves of 96x32
     {256, 256, 4, 4, 32},  // 37: 16 waves of 64x64
     {352, 128, 11, 1, 32}, // 38: 11 waves of 32x128
+    // half-height tiles sized so that two workgroups share a CU (LDS <= 80 KB):
+    // the second workgroup computes while the first waits for its K-tile
+    {176, 128, 1, 8},      // 39: 2 stages, 8 waves of 176x16
+    {176, 128, 1, 4},      // 40: 2 stages, 4 waves of 176x32
+    {192, 128, 2, 2, 32},  // 41: 2 stages, 4 waves of 96x64
+    {192, 128, 2, 4, 32},  // 42: 2 stages, 8 waves of 96x32
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -1307,6 +1314,10 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 36: return go_dl<DT, 384, 128, 4, 4, 4, 4, 32>(a, s);
     case 37: return go_dl<DT, 256, 256, 4, 4, 4, 4, 32>(a, s);
     case 38: return go_dl<DT, 352, 128, 11, 1, 4, 4, 32>(a, s);
+    case 39: return go_dl<DT, 176, 128, 1, 8, 2>(a, s);
+    case 40: return go_dl<DT, 176, 128, 1, 4, 2>(a, s);
+    case 41: return go_dl<DT, 192, 128, 2, 2, 2, 8, 32>(a, s);
+    case 42: return go_dl<DT, 192, 128, 2, 4, 2, 8, 32>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -122,11 +122,23 @@ struct dn_net {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t cap_stream = nullptr;       // capture stream (never the legacy null stream)
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    // Two instances of each captured forward, launched alternately: a launch
+    // then never has to wait for the previous replay of the same instance to
+    // retire, so the host can queue the next forward while one runs.
+    struct GraphPair { hipGraphExec_t exec[2] = {nullptr, nullptr}; unsigned next = 0; };
+    std::map<GraphKey, GraphPair> graphs;
     std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
     std::mutex mu;
 };
+
+static void drop_graphs(dn_net *net)
+{
+    for (auto &kv : net->graphs)
+        for (hipGraphExec_t e : kv.second.exec)
+            if (e) (void)hipGraphExecDestroy(e);
+    net->graphs.clear();
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -160,15 +172,25 @@ static dn_status check_dtype(int dt)
     return DN_OK;
 }
 
-// Heuristic tile when the autotuner has not run: largest tile that still
-// gives >= 1 workgroup per CU, small-N tiles for narrow layers.
+// Heuristic tile when the autotuner has not run: the 176x128 LDS-DMA tile
+// (two workgroups per CU) when it yields about one round of work, else the
+// largest tile that still gives >= 1 workgroup per CU, small-N tiles for
+// narrow layers, split-K when the grid stays small.
 static void heuristic_tile(int M, int N, int K, int *tile, int *splits)
 {
     const int CUS = 256;
+    static const int TILE_176x128 = [] {
+        for (int t = 0; t < tile_count(); ++t) {
+            const TileCfg c = tile_cfg(t);
+            if (c.bm == 176 && c.bn == 128 && c.wm == 1 && c.wn == 8) return t;
+        }
+        return 2;
+    }();
     int best = 2;
     if (N <= 16) best = 6;
     else if (N <= 32) best = 7;
     else if (N <= 64) best = (M >= 256 * 64) ? 1 : 0;
+    else if ((long)((M + 175) / 176) * ((N + 127) / 128) >= CUS - 16) best = TILE_176x128;
     else {
         const int cands[] = {4, 3, 2, 8, 0};
         best = 0;
@@ -589,7 +611,7 @@ extern "C" void dn_net_destroy(dn_net *net)
     if (!net) return;
     (void)hipSetDevice(net->o.device);
     (void)hipDeviceSynchronize();
-    for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
+    drop_graphs(net);
     for (auto &cw : net->cw) free_weights(cw);
     for (auto &kv : net->host_vals)
         for (unsigned char *b : kv.second) (void)hipHostFree(b);
@@ -711,8 +733,7 @@ extern "C" dn_status dn_load_weights(dn_net *net, int layer, const double *w, co
     }
     cw.loaded = true;
     net->calibrated = false;
-    for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
-    net->graphs.clear();
+    drop_graphs(net);
     return DN_OK;
 }
 
@@ -732,7 +753,7 @@ static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, 
     {
         std::lock_guard<std::mutex> g(net->mu);
         auto it = net->graphs.find(key);
-        if (it != net->graphs.end()) exec = it->second;
+        if (it != net->graphs.end()) exec = it->second.exec[it->second.next++ & 1];
     }
     if (!exec) {
         hipGraph_t graph = nullptr;
@@ -744,11 +765,18 @@ static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, 
             return rc;
         }
         if (e != hipSuccess) return fail(DN_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        dn_net::GraphPair gp;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphInstantiate(&gp.exec[i], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return fail(DN_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            for (hipGraphExec_t x2 : gp.exec)
+                if (x2) (void)hipGraphExecDestroy(x2);
+            return fail(DN_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+        exec = gp.exec[0];
+        gp.next = 1;
         std::lock_guard<std::mutex> g(net->mu);
-        net->graphs[key] = exec;
+        net->graphs[key] = gp;
     }
     HIPCHK(hipGraphLaunch(exec, s));
     return DN_OK;
@@ -884,8 +912,7 @@ extern "C" dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h,
     if (rc == DN_OK) {
         std::lock_guard<std::mutex> g(net->mu);
         net->calibrated = true;
-        for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
-        net->graphs.clear();
+        drop_graphs(net);
     }
     return rc;
 }
@@ -986,8 +1013,7 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
     if (rc == DN_OK) {
         std::lock_guard<std::mutex> g(net->mu);
         save_tune_cache(net);
-        for (auto &kv : net->graphs) (void)hipGraphExecDestroy(kv.second);
-        net->graphs.clear();
+        drop_graphs(net);
     }
     return rc;
 }
