@@ -356,6 +356,42 @@ def main():
                           % (dom, per_layer[dom]["tile"], _tile_desc(dn, per_layer[dom]["tile"]), *flops[dom][1:]),
                 "avg_launch_ms": dom_ms}
 
+    # the matrix-core rate the chip sustains at its running clock (MFMA-only kernel)
+    measured_peak = {name: dn.mfma_peak(dt) for name, dt in (("bf16", dn.BF16), ("fp8", dn.FP8), ("f32", dn.F32))}
+    roofline["measured_mfma_peak"] = measured_peak["bf16"]
+    roofline["frac_of_measured_peak"] = roofline["achieved"] / measured_peak["bf16"]
+    log("[bench] measured MFMA peak: %s TFLOP/s" % {k: round(v, 1) for k, v in measured_peak.items()})
+
+    cross = None
+    if not args.no_secondary:
+        # reference points from the vendor libraries (never in the product path):
+        # hipBLASLt on the same GEMM shape without the im2col gather, MIOpen's conv
+        M, N, K = flops[dom][1:]
+        a_m = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b_m = torch.randn(K, N, device="cuda", dtype=torch.bfloat16)
+        xc = torch.randn(B, K // 9, 13, 13, device="cuda", dtype=torch.bfloat16).to(memory_format=torch.channels_last)
+        wc = torch.randn(N, K // 9, 3, 3, device="cuda", dtype=torch.bfloat16).to(memory_format=torch.channels_last)
+
+        def t_ms(fn, it=30):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(it):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / it
+
+        mm = t_ms(lambda: torch.matmul(a_m, b_m))
+        cv = t_ms(lambda: torch.nn.functional.conv2d(xc, wc, padding=1))
+        cross = {"hipblaslt_gemm_same_shape_ms": mm, "hipblaslt_tflops": flops[dom][0] / (mm * 1e-3) / 1e12,
+                 "miopen_conv_nhwc_ms": cv, "miopen_tflops": flops[dom][0] / (cv * 1e-3) / 1e12,
+                 "this_kernel_ms": dom_ms}
+        log("[bench] cross-check: hipBLASLt %.4f ms, MIOpen %.4f ms, this kernel %.4f ms" % (mm, cv, dom_ms))
+        del a_m, b_m, xc, wc
+
     secondary = []
     if not args.no_secondary:
         # PCIe-inclusive rate: pinned host input -> H2D -> forward -> D2H, serialised on one stream
@@ -428,6 +464,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_b64, 50)), "p99": float(np.percentile(lat_b64, 99)),
                        "replays": len(lat_b64)},
         "roofline": roofline,
+        "mfma_measured_peak_tflops": measured_peak,
+        "dominant_conv_cross_check": cross,
         "cpu_baseline": cpu,
         "per_conv": {str(k): v for k, v in per_layer.items()},
         "secondary": secondary,

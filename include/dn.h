@@ -218,6 +218,15 @@ dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, f
 dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
                     float *y, void *stream);
 
+/* Measurement helper: the matrix-core throughput the device sustains for the
+ * MFMA instruction the convolutions of `dtype` use (16x16x4 FP32, 16x16x32
+ * BF16, 16x16x128 FP8), from a kernel that only multiplies (8 waves per SIMD,
+ * 8 independent accumulators per wave, no memory traffic); best of three
+ * timed launches, in TFLOP/s.  Synchronous; allocates and frees a small
+ * device buffer.  DN_EINVAL for a NULL pointer or unknown dtype, DN_EHIP on
+ * a HIP failure. */
+dn_status dn_mfma_peak(int dtype, int device, double *tflops);
+
 /* Number of compiled conv tile configurations and their shapes: output tile
  * bm x bn, waves_m x waves_n waves, and the side of the MFMA blocks a BF16
  * conv uses with it (16 or 32; other dtypes always use 16x16 blocks).  Tiles

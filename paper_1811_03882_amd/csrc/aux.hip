@@ -355,4 +355,82 @@ hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- MFMA peak probe
+// Measurement only: every wave keeps eight independent accumulator chains of
+// one MFMA instruction busy (no memory traffic), so the achieved rate is the
+// matrix-core throughput at the clock the chip actually runs.  The chains are
+// written as one asm block so that the compiler cannot insert copies between
+// dependent instructions; each accumulator is reused only after seven others.
+typedef float pf4 __attribute__((ext_vector_type(4)));
+typedef int pi8 __attribute__((ext_vector_type(8)));
+typedef unsigned pu4 __attribute__((ext_vector_type(4)));
+
+template <int DT>
+__global__ void __launch_bounds__(256) mfma_peak_kernel(float *out, int iters)
+{
+    pf4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = c0, c2 = c0, c3 = c0, c4 = c0, c5 = c0, c6 = c0, c7 = c0;
+    const unsigned v = 0x3c003c00u + threadIdx.x;  // small finite operands
+    for (int it = 0; it < iters; ++it) {
+        if constexpr (DT == BF16) {
+            const pu4 a = {v, v + 1, v + 2, v + 3};
+            asm volatile(
+                "v_mfma_f32_16x16x32_bf16 %0, %8, %8, %0\n\t"
+                "v_mfma_f32_16x16x32_bf16 %1, %8, %8, %1\n\t"
+                "v_mfma_f32_16x16x32_bf16 %2, %8, %8, %2\n\t"
+                "v_mfma_f32_16x16x32_bf16 %3, %8, %8, %3\n\t"
+                "v_mfma_f32_16x16x32_bf16 %4, %8, %8, %4\n\t"
+                "v_mfma_f32_16x16x32_bf16 %5, %8, %8, %5\n\t"
+                "v_mfma_f32_16x16x32_bf16 %6, %8, %8, %6\n\t"
+                "v_mfma_f32_16x16x32_bf16 %7, %8, %8, %7"
+                : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(c4), "+v"(c5), "+v"(c6), "+v"(c7)
+                : "v"(a));
+        } else if constexpr (DT == FP8) {
+            const pi8 a = {(int)v, (int)v, (int)v, (int)v, (int)v, (int)v, (int)v, (int)v};
+            asm volatile(
+                "v_mfma_f32_16x16x128_f8f6f4 %0, %8, %8, %0\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %1, %8, %8, %1\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %2, %8, %8, %2\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %3, %8, %8, %3\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %4, %8, %8, %4\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %5, %8, %8, %5\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %6, %8, %8, %6\n\t"
+                "v_mfma_f32_16x16x128_f8f6f4 %7, %8, %8, %7"
+                : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(c4), "+v"(c5), "+v"(c6), "+v"(c7)
+                : "v"(a));
+        } else {
+            const float a = __uint_as_float(0x3f800000u + threadIdx.x);
+            asm volatile(
+                "v_mfma_f32_16x16x4_f32 %0, %8, %8, %0\n\t"
+                "v_mfma_f32_16x16x4_f32 %1, %8, %8, %1\n\t"
+                "v_mfma_f32_16x16x4_f32 %2, %8, %8, %2\n\t"
+                "v_mfma_f32_16x16x4_f32 %3, %8, %8, %3\n\t"
+                "v_mfma_f32_16x16x4_f32 %4, %8, %8, %4\n\t"
+                "v_mfma_f32_16x16x4_f32 %5, %8, %8, %5\n\t"
+                "v_mfma_f32_16x16x4_f32 %6, %8, %8, %6\n\t"
+                "v_mfma_f32_16x16x4_f32 %7, %8, %8, %7"
+                : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(c4), "+v"(c5), "+v"(c6), "+v"(c7)
+                : "v"(a));
+        }
+    }
+    const float r = c0[0] + c1[1] + c2[2] + c3[3] + c4[0] + c5[1] + c6[2] + c7[3];
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+double mfma_peak_flops_per_launch(int dt, int blocks, int iters)
+{
+    const double per = dt == FP8 ? 16.0 * 16 * 128 * 2 : dt == BF16 ? 16.0 * 16 * 32 * 2 : 16.0 * 16 * 4 * 2;
+    return (double)blocks * 4 /* waves */ * iters * 8 /* MFMAs per iteration */ * per;
+}
+
+hipError_t launch_mfma_peak(int dt, float *out, int blocks, int iters, hipStream_t s)
+{
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(mfma_peak_kernel<F32>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case BF16: hipLaunchKernelGGL(mfma_peak_kernel<BF16>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case FP8: hipLaunchKernelGGL(mfma_peak_kernel<FP8>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace dnk

@@ -114,5 +114,9 @@ hipError_t launch_add(int dt, const void *a, float sa, const void *b, float sb, 
 // amax of |x| over `count` FP32 values, max-combined into *out (caller zeroes *out).
 hipError_t launch_amax(const float *x, size_t count, float *out, hipStream_t s);
 hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s);
+// MFMA-only throughput probe (measurement): blocks x 256 threads, out holds
+// blocks * 256 floats.
+hipError_t launch_mfma_peak(int dt, float *out, int blocks, int iters, hipStream_t s);
+double mfma_peak_flops_per_launch(int dt, int blocks, int iters);
 
 }  // namespace dnk

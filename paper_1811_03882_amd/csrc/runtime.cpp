@@ -1036,6 +1036,43 @@ extern "C" dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int 
     return fail(DN_EINVAL, "layer %d is not a conv layer", layer);
 }
 
+extern "C" dn_status dn_mfma_peak(int dtype, int device, double *tflops)
+{
+    if (!tflops) return fail(DN_EINVAL, "tflops is NULL");
+    STCHK(check_dtype(dtype));
+    HIPCHK(hipSetDevice(device));
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    const int blocks = cus * 8, iters = dtype == FP8 ? 2000 : 4000;  // 8 waves per SIMD
+    float *out = nullptr;
+    HIPCHK(hipMalloc(&out, (size_t)blocks * 256 * sizeof(float)));
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    dn_status rc = DN_OK;
+    float best = 0.f;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        rc = fail(DN_EHIP, "stream / event creation failed");
+    if (rc == DN_OK && (launch_mfma_peak(dtype, out, blocks, 200, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+        rc = fail(DN_EHIP, "probe warm-up failed");
+    for (int rep = 0; rep < 3 && rc == DN_OK; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess || launch_mfma_peak(dtype, out, blocks, iters, s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(DN_EHIP, "probe launch failed");
+            break;
+        }
+        if (best == 0.f || ms < best) best = ms;
+    }
+    if (rc == DN_OK) *tflops = mfma_peak_flops_per_launch(dtype, blocks, iters) / (best * 1e-3) / 1e12;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(out);
+    return rc;
+}
+
 extern "C" dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int w, int iters, void *stream, float *avg_ms)
 {
     if (!net || !avg_ms || iters <= 0) return fail(DN_EINVAL, "bad argument");

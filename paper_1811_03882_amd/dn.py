@@ -85,6 +85,7 @@ SIGNATURES = {
     "dn_egress": (_i, [_i, _i, _i, _i, _i, _vp, _f, _vp, _vp]),
     "dn_tile_count": (_i, []),
     "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip, _ip]),
+    "dn_mfma_peak": (_i, [_i, _i, ctypes.POINTER(ctypes.c_double)]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -157,6 +158,13 @@ def channel_pad(dtype: int, c: int) -> int:
 
 def tile_count() -> int:
     return LIB.dn_tile_count()
+
+
+def mfma_peak(dtype: int, device: int = 0) -> float:
+    """Sustained MFMA throughput (TFLOP/s) of the instruction dtype's convs use."""
+    v = ctypes.c_double()
+    check(LIB.dn_mfma_peak(dtype, device, ctypes.byref(v)))
+    return v.value
 
 
 def tile_info(t: int) -> Tuple[int, int, int, int, int]:

@@ -279,6 +279,18 @@ def test_shortcut_f32_exact(dn):
     np.testing.assert_array_equal(got, (a.astype(np.float32) + b.astype(np.float32)).astype(np.float64))
 
 
+def test_mfma_peak_probe(dn):
+    """The throughput probe runs for every dtype and reports a rate between a
+    tenth of and just above the datasheet dense peak."""
+    datasheet = {dn.F32: 157.3, dn.BF16: 2516.6, dn.FP8: 5033.2}
+    for dt, peak in datasheet.items():
+        got = dn.mfma_peak(dt)
+        print("MFMA probe dtype %d: %.1f TFLOP/s (datasheet %.1f)" % (dt, got, peak))
+        assert 0.1 * peak < got < 1.05 * peak
+    with pytest.raises(dn.DnError):
+        dn.mfma_peak(9)
+
+
 def test_bad_arguments_are_rejected(dn):
     d = dn.conv_desc(1, 13, 13, 8, 8, 3, 1, 1, pool=2)  # odd output cannot take the fused pool
     with pytest.raises(dn.DnError) as e:
