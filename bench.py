@@ -420,6 +420,28 @@ def main():
                               "dominant_conv_pct_peak": 100.0 * flops[dom][0] / (l13 * 1e-3) / PEAK[name]})
             n2.close()
             del a2
+        # detection post-processing on the device (decode + per-class NMS) for
+        # one batch of region outputs of the 9-layer head (64 x 125 x 13 x 13)
+        log("[bench] detection post-processing b64")
+        A_, C_, md = 5, 20, 50
+        yr = torch.from_numpy(synth.region_output(B, A_, C_, 13, 13, tag=64, clusters=3)).cuda()
+        wsb = dn.detect_workspace(B, A_, C_, 13, 13)
+        wsd = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        dets = torch.empty((B, C_, md, 5), device="cuda")
+        didx = torch.empty((B, C_, md), dtype=torch.int32, device="cuda")
+        dcnt = torch.empty((B, C_), dtype=torch.int32, device="cuda")
+        anc = synth.region_anchors(A_)
+        run = lambda: dn.detect(yr, B, A_, C_, 13, 13, anc, 0.2, 0.45, md, wsd, wsb, dets, didx, dcnt, stream)
+        with torch.cuda.stream(stream):
+            wd, pd = time_steps(torch, run, 50, 5, stream)
+        secondary.append({"workload": "detection post-processing, 64 images x 13x13x5 boxes x 20 classes "
+                                      "(region decode + per-class greedy NMS, thresh 0.2, IoU 0.45)",
+                          "ms_per_batch": float(np.percentile(pd, 50)), "kept_boxes": int(dcnt.sum().item()),
+                          "region_tensor_bytes": int(yr.numel() * 4),
+                          "kept_box_bytes": int(dcnt.sum().item()) * 24})
+        log("[bench] detection: %.4f ms per batch, %d boxes kept" % (np.percentile(pd, 50), int(dcnt.sum().item())))
+        del yr, wsd, dets, didx, dcnt
+
         # FP32 plain path, batch 1: resident (graph) vs per-layer transfers
         x1 = x[:1].contiguous()
         y1 = torch.empty((1,) + out_shape, dtype=torch.float32, device="cuda")

@@ -218,6 +218,33 @@ dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, f
 dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
                     float *y, void *stream);
 
+/* ---- detection post-processing (the workload's detection program, Sec.
+ * 5.1.1; the paper gives no decoding rule, so this one is a stated reading).
+ * y: device, [batch][anchors*(5+classes)][h][w] FP32, the dn_forward output of
+ * a region head: per anchor a, channels a*(5+classes) + (0..4) are
+ * tx, ty, tw, th, to and the next `classes` channels are class logits.
+ * Box index b = (i*w + j)*anchors + a for grid cell (row i, column j).
+ * Box (centre x, centre y, width, height) in image fractions:
+ *   ((j + sigmoid(tx)) / w, (i + sigmoid(ty)) / h,
+ *    anchor_w * exp(tw) / w, anchor_h * exp(th) / h);
+ * score of class k = sigmoid(to) * softmax(logits)[k].
+ * Per image and class: candidates with score >= thresh, ranked by score
+ * (descending; ties by box index ascending), are kept greedily unless a kept
+ * box overlaps them with IoU > nms_thresh; at most max_det are kept.
+ * Outputs (device, caller-owned): dets [batch][classes][max_det][5] = score,
+ * x, y, w, h; det_index [batch][classes][max_det]; counts [batch][classes]
+ * (entries past counts are left untouched).  anchor_wh: host, 2*anchors
+ * floats (w, h per anchor, in grid cells), copied at the call.
+ * workspace: device, at least dn_detect_workspace() bytes.  Enqueue only.
+ * Limits: anchors <= 16, h*w*anchors <= 4096, else DN_EUNSUPPORTED;
+ * non-positive sizes, NULL pointers, NaN thresholds or a short workspace are
+ * DN_EINVAL.  Decisions are taken in FP32. */
+dn_status dn_detect_workspace(int batch, int anchors, int classes, int h, int w, size_t *bytes);
+dn_status dn_detect(const float *y, int batch, int anchors, int classes, int h, int w,
+                    const float *anchor_wh, float thresh, float nms_thresh, int max_det,
+                    void *workspace, size_t ws_bytes, float *dets, int *det_index, int *counts,
+                    void *stream);
+
 /* Measurement helper: the matrix-core throughput the device sustains for the
  * MFMA instruction the convolutions of `dtype` use (16x16x4 FP32, 16x16x32
  * BF16, 16x16x128 FP8), from a kernel that only multiplies (8 waves per SIMD,

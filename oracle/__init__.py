@@ -16,6 +16,9 @@ under ``tests/test_oracle_*.py``):
   conv2d, add_bias, batchnorm, leaky, maxpool, shortcut: pinned.
   net forward: composition of the pinned layers; pinned by layer-by-layer
   recomputation and by identity-unit constructions.
+  detect (``detect.py``, region decode + per-class NMS, FP32 like the device
+  kernels): pinned by hand-computed boxes, closed-form IoUs, and brute-force
+  checks of the suppression invariants.
 """
 from __future__ import annotations
 

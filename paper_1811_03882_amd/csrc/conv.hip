@@ -950,6 +950,15 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Division by a runtime divisor d >= 1 without the integer-divide sequence:
+// q = umulhi(n, ceil(2^32 / d)) is exact whenever n * d < 2^32 (true for
+// every LDS index here).
+struct FastDiv {
+    unsigned m, d;
+    __device__ explicit FastDiv(unsigned d_) : m(d_ > 1 ? 0xFFFFFFFFu / d_ + 1u : 0u), d(d_) {}
+    __device__ __forceinline__ unsigned div(unsigned n) const { return d > 1 ? __umulhi(n, m) : n; }
+};
+
 // ---------------------------------------------------------------- halo kernel
 // Small convolutions (K = R*S*Cin_p up to HALO_KMAX elements, Cout <= 64):
 // one workgroup owns a TH x 32 output tile and every output channel.  Its
@@ -981,7 +990,9 @@ constexpr int HALO_LDS_MAX = 96 * 1024;
 
 bool halo_ok(int dt, const ConvArgs &a)
 {
-    return kblock_ch(dt, a.cin_p, a.R * a.S) == a.cin_p && a.R * a.S * a.cin_p * esize(dt) <= HALO_KMAX_BYTES && a.cout_p <= 64 && a.stride <= 2 &&
+    return kblock_ch(dt, a.cin_p, a.R * a.S) == a.cin_p && a.R * a.S * a.cin_p * esize(dt) <= HALO_KMAX_BYTES &&
+           a.cout_p <= 64 && a.stride <= 2 && (size_t)a.Ho * a.Wo * a.cout_p < (1u << 31) &&
+           (size_t)a.H * a.W * a.cin_p * esize(dt) < (1u << 31) &&
            halo_lds_bytes(dt, a, 8) <= HALO_LDS_MAX;
 }
 
@@ -1018,17 +1029,20 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     {
         const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
         const int tot = LH * LW * cps;
+        const FastDiv by_cps(cps), by_lw(LW);
+        const unsigned char *ximg = reinterpret_cast<const unsigned char *>(a.x) + (size_t)n * a.H * a.W * a.cin_p * ES;
         for (int base = 0; base < tot; base += 256 * 8) {
             u32x4 v[8];
             int dst[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int e = base + j * 256 + tid;
-                const int ch = e % cps, px = e / cps, lc = px % LW, lr = px / LW;
+                const int px = by_cps.div(e), ch = e - px * cps;
+                const int lr = by_lw.div(px), lc = px - lr * LW;
                 const int hi = hi0 + lr, wi = wi0 + lc;
                 const bool ok = e < tot && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
-                const size_t off = ok ? ((((size_t)n * a.H + hi) * a.W + wi) * a.cin_p + ch * SEG) * ES : 0;
-                v[j] = ok ? gload16(a.x, off) : z4;
+                const unsigned off = ok ? (unsigned)(((hi * a.W + wi) * a.cin_p + ch * SEG) * ES) : 0u;
+                v[j] = ok ? gload16(ximg, off) : z4;
                 dst[j] = e < tot ? px * pst + ch : -1;
             }
 #pragma unroll
@@ -1037,8 +1051,9 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
         }
         // weights: rows [cout_p][KS*KSTEP] (K beyond k_pad reads as zero)
         const int wtot = nb_count * 16 * wch;
+        const FastDiv by_wch(wch);
         for (int e = tid; e < wtot; e += 256) {
-            const int ch = e % wch, row = e / wch;
+            const int row = by_wch.div(e), ch = e - row * wch;
             const bool ok = row < a.cout_p && (ch + 1) * 16 <= a.k_pad * ES;
             wlds[row * wst + ch] = ok ? gload16(a.w, (size_t)row * a.k_pad * ES + ch * 16) : z4;
         }
@@ -1106,7 +1121,11 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     }
 
     // ---- epilogue: bias, activation, [residual], [2x2 max], round, NHWC store
+    // (offsets inside one image fit in 32 bits: checked by halo_ok)
     const int Hp = a.Ho >> 1, Wp = a.Wo >> 1;
+    const size_t img = POOL ? (size_t)Hp * Wp * a.cout_p : (size_t)a.Ho * a.Wo * a.cout_p;
+    unsigned char *yimg = reinterpret_cast<unsigned char *>(a.y) + (size_t)n * img * ES;
+    const unsigned char *rimg = a.res ? reinterpret_cast<const unsigned char *>(a.res) + (size_t)n * img * ES : nullptr;
 #pragma unroll
     for (int nb = 0; nb < MAXNB; ++nb) {
         if (nb >= nb_count) break;
@@ -1124,7 +1143,7 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
                 const float o = activate(mx * scl + bias, a.act, a.slope) * a.out_inv_scale;
                 const int rp = b / (HT_W / 8), wg = b % (HT_W / 8);
                 const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
-                if (hp < Hp && wp < Wp) store_el<DT>(a.y, (((size_t)n * Hp + hp) * Wp + wp) * a.cout_p + col, o);
+                if (hp < Hp && wp < Wp) store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
             } else {
                 float v[4];
 #pragma unroll
@@ -1135,10 +1154,10 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
                     for (int q = 0; q < 4; ++q) {
                         const int wo = tw0 + (b % (HT_W / 16)) * 16 + 4 * lgrp + q;
                         if (wo >= a.Wo) continue;
-                        const size_t o = (((size_t)n * a.Ho + ho) * a.Wo + wo) * a.cout_p + col;
+                        const int o = (ho * a.Wo + wo) * a.cout_p + col;
                         float r = v[q];
-                        if (a.res) r += load_el<DT>(a.res, o) * a.res_scale;
-                        store_el<DT>(a.y, o, r * a.out_inv_scale);
+                        if (rimg) r += load_el<DT>(rimg, o) * a.res_scale;
+                        store_el<DT>(yimg, o, r * a.out_inv_scale);
                     }
                 }
             }

@@ -114,6 +114,24 @@ hipError_t launch_add(int dt, const void *a, float sa, const void *b, float sb, 
 // amax of |x| over `count` FP32 values, max-combined into *out (caller zeroes *out).
 hipError_t launch_amax(const float *x, size_t count, float *out, hipStream_t s);
 hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s);
+// Region decode + per-class NMS (detect.hip).
+constexpr int DETECT_MAX_ANCHORS = 16;
+constexpr int DETECT_MAX_BOXES = 4096;  // H * W * A per image (sorted in LDS)
+struct DetectArgs {
+    const float *y;                       // [N][A*(5+C)][H][W] FP32
+    float anchors[2 * DETECT_MAX_ANCHORS]; // (w, h) per anchor, in grid cells
+    int N, A, C, H, W;
+    float thresh, nms_thresh;
+    int max_det;                          // kept boxes per image and class (capacity)
+    float *score;                         // workspace [N][C][H*W*A]
+    float *box;                           // workspace [N][H*W*A][4]
+    float *dets;                          // [N][C][max_det][5]: score, x, y, w, h
+    int *det_index;                       // [N][C][max_det]: box index (i*W + j)*A + a
+    int *counts;                          // [N][C]
+};
+hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
+size_t detect_nms_lds(int boxes);
+
 // MFMA-only throughput probe (measurement): blocks x 256 threads, out holds
 // blocks * 256 floats.
 hipError_t launch_mfma_peak(int dt, float *out, int blocks, int iters, hipStream_t s);

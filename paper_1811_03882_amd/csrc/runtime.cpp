@@ -1036,6 +1036,52 @@ extern "C" dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int 
     return fail(DN_EINVAL, "layer %d is not a conv layer", layer);
 }
 
+// ---------------------------------------------------------------- detection
+
+static dn_status detect_check(int batch, int anchors, int classes, int h, int w)
+{
+    if (batch <= 0 || anchors <= 0 || classes <= 0 || h <= 0 || w <= 0)
+        return fail(DN_EINVAL, "detect: non-positive size");
+    if (anchors > DETECT_MAX_ANCHORS) return fail(DN_EUNSUPPORTED, "detect: at most %d anchors", DETECT_MAX_ANCHORS);
+    if ((long)h * w * anchors > DETECT_MAX_BOXES)
+        return fail(DN_EUNSUPPORTED, "detect: h*w*anchors must be <= %d", DETECT_MAX_BOXES);
+    return DN_OK;
+}
+
+extern "C" dn_status dn_detect_workspace(int batch, int anchors, int classes, int h, int w, size_t *bytes)
+{
+    if (!bytes) return fail(DN_EINVAL, "bytes is NULL");
+    STCHK(detect_check(batch, anchors, classes, h, w));
+    const size_t B = (size_t)h * w * anchors;
+    *bytes = align256((size_t)batch * classes * B * 4) + (size_t)batch * B * 16;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_detect(const float *y, int batch, int anchors, int classes, int h, int w,
+                               const float *anchor_wh, float thresh, float nms_thresh, int max_det,
+                               void *workspace, size_t ws_bytes, float *dets, int *det_index, int *counts,
+                               void *stream)
+{
+    STCHK(detect_check(batch, anchors, classes, h, w));
+    if (!y || !anchor_wh || !workspace || !dets || !det_index || !counts) return fail(DN_EINVAL, "detect: NULL pointer");
+    if (max_det <= 0) return fail(DN_EINVAL, "detect: max_det must be positive");
+    if (!(thresh == thresh) || !(nms_thresh == nms_thresh)) return fail(DN_EINVAL, "detect: NaN threshold");
+    size_t need = 0;
+    STCHK(dn_detect_workspace(batch, anchors, classes, h, w, &need));
+    if (ws_bytes < need) return fail(DN_EINVAL, "detect: workspace has %zu bytes, needs %zu", ws_bytes, need);
+    DetectArgs a{};
+    a.y = y;
+    for (int i = 0; i < 2 * anchors; ++i) a.anchors[i] = anchor_wh[i];
+    a.N = batch; a.A = anchors; a.C = classes; a.H = h; a.W = w;
+    a.thresh = thresh; a.nms_thresh = nms_thresh; a.max_det = max_det;
+    const size_t B = (size_t)h * w * anchors;
+    a.score = (float *)workspace;
+    a.box = (float *)((char *)workspace + align256((size_t)batch * classes * B * 4));
+    a.dets = dets; a.det_index = det_index; a.counts = counts;
+    HIPCHK(launch_detect(a, (hipStream_t)stream));
+    return DN_OK;
+}
+
 extern "C" dn_status dn_mfma_peak(int dtype, int device, double *tflops)
 {
     if (!tflops) return fail(DN_EINVAL, "tflops is NULL");

@@ -86,6 +86,9 @@ SIGNATURES = {
     "dn_tile_count": (_i, []),
     "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip, _ip]),
     "dn_mfma_peak": (_i, [_i, _i, ctypes.POINTER(ctypes.c_double)]),
+    "dn_detect_workspace": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "dn_detect": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_float), _f, _f, _i, _vp, _sz, _vp, _vp,
+                       _vp, _vp]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -158,6 +161,20 @@ def channel_pad(dtype: int, c: int) -> int:
 
 def tile_count() -> int:
     return LIB.dn_tile_count()
+
+
+def detect_workspace(batch: int, anchors: int, classes: int, h: int, w: int) -> int:
+    v = _sz()
+    check(LIB.dn_detect_workspace(batch, anchors, classes, h, w, ctypes.byref(v)))
+    return v.value
+
+
+def detect(y, batch, anchors, classes, h, w, anchor_wh, thresh, nms_thresh, max_det, workspace, ws_bytes,
+           dets, det_index, counts, stream=None):
+    """Region decode + per-class NMS on the device (see dn_detect)."""
+    aw = (ctypes.c_float * len(anchor_wh))(*[float(v) for v in anchor_wh])
+    check(LIB.dn_detect(ptr(y), batch, anchors, classes, h, w, aw, float(thresh), float(nms_thresh), max_det,
+                        ptr(workspace), ws_bytes, ptr(dets), ptr(det_index), ptr(counts), stream_handle(stream)))
 
 
 def mfma_peak(dtype: int, device: int = 0) -> float:

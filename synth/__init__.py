@@ -162,6 +162,7 @@ def make_tensor(shape, seed: int, tag: int, lo: float = -1.0, hi: float = 1.0) -
 
 # Seeds used throughout (a stated choice; the distributions above fix the rest).
 SEED_SINGLE, SEED_PLAIN, SEED_RESIDUAL, SEED_SERVING, SEED_CALIB = 0, 1, 2, 3, 4
+SEED_DETECT = 5
 
 
 @dataclass
@@ -183,3 +184,33 @@ def serving_trace(n_requests: int = 10000, rate: float = 2000.0, seed: int = SEE
 def serving_image(i: int, side: int, seed: int = SEED_SERVING, in_c: int = 3) -> np.ndarray:
     rng = np.random.default_rng([seed, 4, i])
     return rng.uniform(0.0, 1.0, size=(1, in_c, side, side))
+
+
+def region_anchors(anchors: int, seed: int = SEED_DETECT) -> np.ndarray:
+    """Anchor (w, h) pairs in grid cells, uniform over [0.5, 12), rng [seed, 6]."""
+    return np.random.default_rng([seed, 6]).uniform(0.5, 12.0, 2 * anchors)
+
+
+def region_output(n: int, anchors: int, classes: int, h: int, w: int, seed: int = SEED_DETECT,
+                  tag: int = 0, clusters: int = 0) -> np.ndarray:
+    """A synthetic region-head output [n, anchors*(5+classes), h, w] FP32, rng
+    [seed, 7, tag]: tx, ty ~ N(0, 1), tw, th ~ N(0, 0.5), to ~ N(-1, 2), class
+    logits ~ N(0, 2).  With clusters > 0, that many cells per image get a
+    confident object (to = 4, one class logit + 6) in every anchor, and their
+    neighbours repeat it, so that many overlapping boxes compete in NMS."""
+    rng = np.random.default_rng([seed, 7, tag])
+    y = np.empty((n, anchors, 5 + classes, h, w), np.float32)
+    y[:, :, 0:2] = rng.normal(0.0, 1.0, (n, anchors, 2, h, w))
+    y[:, :, 2:4] = rng.normal(0.0, 0.5, (n, anchors, 2, h, w))
+    y[:, :, 4] = rng.normal(-1.0, 2.0, (n, anchors, h, w))
+    y[:, :, 5:] = rng.normal(0.0, 2.0, (n, anchors, classes, h, w))
+    for i in range(n):
+        for _ in range(clusters):
+            ci, cj, k = rng.integers(0, h), rng.integers(0, w), rng.integers(0, classes)
+            for di in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    ii, jj = ci + di, cj + dj
+                    if 0 <= ii < h and 0 <= jj < w:
+                        y[i, :, 4, ii, jj] = 4.0 - abs(di) - abs(dj)
+                        y[i, :, 5 + k, ii, jj] += 6.0
+    return y.reshape(n, anchors * (5 + classes), h, w)

@@ -100,3 +100,19 @@ def test_null_safe_destroy(dn):
     dn.LIB.dn_net_destroy(None)
     st = dn.LIB.dn_forward(None, None, 1, 1, 1, None, None)
     assert st == dn.DN_EINVAL
+
+
+def test_detect_workspace_and_validation(dn):
+    assert dn.detect_workspace(2, 5, 20, 13, 13) == ((2 * 20 * 845 * 4 + 255) // 256) * 256 + 2 * 845 * 16
+    with pytest.raises(dn.DnError) as e:
+        dn.detect_workspace(1, 17, 20, 13, 13)                      # more than 16 anchors
+    assert e.value.status == dn.DN_EUNSUPPORTED
+    with pytest.raises(dn.DnError) as e:
+        dn.detect_workspace(1, 5, 20, 40, 40)                       # 8000 boxes > 4096
+    assert e.value.status == dn.DN_EUNSUPPORTED
+    with pytest.raises(dn.DnError) as e:
+        dn.detect_workspace(0, 5, 20, 13, 13)
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:                            # NULL buffers are refused before any launch
+        dn.detect(None, 1, 5, 20, 13, 13, [1.0] * 10, 0.2, 0.45, 10, None, 0, None, None, None)
+    assert e.value.status == dn.DN_EINVAL
