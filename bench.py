@@ -442,6 +442,39 @@ def main():
         log("[bench] detection: %.4f ms per batch, %d boxes kept" % (np.percentile(pd, 50), int(dcnt.sum().item())))
         del yr, wsd, dets, didx, dcnt
 
+        # Jacobi/Laplace (the paper's second example of the transfer rule):
+        # 4096 x 4096 FP64 grid, device-resident vs copied across PCIe every iteration
+        log("[bench] jacobi 4096x4096")
+        nj = 4096
+        uj = torch.zeros((nj, nj), dtype=torch.float64, device="cuda")
+        uj[0, :] = 1.0
+        wj = torch.empty_like(uj)
+        it_res = 200
+        with torch.cuda.stream(stream):
+            dn.jacobi(uj, wj, nj, nj, 10, None, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dn.jacobi(uj, wj, nj, nj, it_res, None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms_res = e0.elapsed_time(e1) / it_res
+        uh = np.zeros((nj, nj), np.float64)
+        uh[0, :] = 1.0
+        t0 = time.perf_counter()
+        it_pl = 5
+        dn.jacobi_per_iteration(uh, uj, wj, it_pl, stream)
+        ms_pl = (time.perf_counter() - t0) * 1e3 / it_pl
+        jbytes = 2 * 8 * nj * nj
+        secondary.append({"workload": "Jacobi/Laplace 4096x4096 FP64: device-resident vs per-iteration transfer",
+                          "resident_ms_per_iteration": ms_res, "per_iteration_transfer_ms_per_iteration": ms_pl,
+                          "speedup_resident": ms_pl / ms_res,
+                          "roofline": {"bound": "hbm", "achieved": jbytes / (ms_res * 1e-3) / 1e9, "peak": 8000.0,
+                                       "unit": "GB/s", "frac": jbytes / (ms_res * 1e-3) / 8e12,
+                                       "algorithmic_bytes_per_iteration": jbytes}})
+        log("[bench] jacobi: resident %.4f ms/iter, per-iteration transfer %.3f ms/iter" % (ms_res, ms_pl))
+        del uj, wj, uh
+
         # FP32 plain path, batch 1: resident (graph) vs per-layer transfers
         x1 = x[:1].contiguous()
         y1 = torch.empty((1,) + out_shape, dtype=torch.float32, device="cuda")

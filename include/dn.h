@@ -218,6 +218,30 @@ dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, f
 dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
                     float *y, void *stream);
 
+/* ---- Jacobi iteration for the Laplace equation: the second program the
+ * paper's transfer rule sped up (Sec. 4, the paragraph before Sec. 5).
+ * u: [n][m] FP64 row-major grid whose first/last rows and columns are fixed
+ * (Dirichlet) values.  One iteration replaces every interior point by
+ * 0.25 * (up + down + left + right), summed in that order (FP64, no fused
+ * multiply-add), from the previous iterate.
+ *
+ * dn_jacobi: device-resident.  u and work are device buffers of n*m doubles
+ * (caller-owned; work is scratch).  Runs `iters` iterations with no host
+ * round-trip; u holds the result.  max_change (device, one double, may be
+ * NULL) receives the largest |change| of the last iteration (0 for
+ * iters = 0).  Enqueue only.
+ *
+ * dn_jacobi_per_iteration: the naive offload, for comparison.  u_host is a
+ * host grid; every iteration copies it to dev_a, runs one step into dev_b,
+ * copies dev_b back to u_host and synchronises.  dev_a, dev_b: device, n*m
+ * doubles each.  max_change_host (may be NULL) as above.  Synchronous.
+ *
+ * Non-positive sizes, negative iterations, NULL grids, or a device pointer
+ * passed as u_host: DN_EINVAL. */
+dn_status dn_jacobi(double *u, double *work, int n, int m, int iters, double *max_change, void *stream);
+dn_status dn_jacobi_per_iteration(double *u_host, double *dev_a, double *dev_b, int n, int m, int iters,
+                                  double *max_change_host, void *stream);
+
 /* ---- detection post-processing (the workload's detection program, Sec.
  * 5.1.1; the paper gives no decoding rule, so this one is a stated reading).
  * y: device, [batch][anchors*(5+classes)][h][w] FP32, the dn_forward output of

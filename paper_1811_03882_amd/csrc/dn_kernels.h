@@ -132,6 +132,11 @@ struct DetectArgs {
 hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
 size_t detect_nms_lds(int boxes);
 
+// One Jacobi iteration of the Laplace equation on an [n][m] FP64 grid
+// (jacobi.hip); max_change (device, may be NULL) receives the bits of the
+// largest interior change.
+hipError_t launch_jacobi_step(const double *u, double *v, int n, int m, unsigned long long *max_change, hipStream_t s);
+
 // MFMA-only throughput probe (measurement): blocks x 256 threads, out holds
 // blocks * 256 floats.
 hipError_t launch_mfma_peak(int dt, float *out, int blocks, int iters, hipStream_t s);

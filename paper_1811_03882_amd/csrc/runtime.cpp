@@ -1036,6 +1036,71 @@ extern "C" dn_status dn_layer_plan(const dn_net *net, int layer, int batch, int 
     return fail(DN_EINVAL, "layer %d is not a conv layer", layer);
 }
 
+// ---------------------------------------------------------------- Jacobi / Laplace
+
+static dn_status jacobi_check(int n, int m, int iters)
+{
+    if (n <= 0 || m <= 0 || iters < 0) return fail(DN_EINVAL, "jacobi: non-positive size or negative iterations");
+    if ((size_t)n * m >= ((size_t)1 << 40)) return fail(DN_EINVAL, "jacobi: grid too large");
+    return DN_OK;
+}
+
+// Device-resident: the grid and its partner buffer stay in HBM for all the
+// iterations; no host round-trip.  u holds the result.
+extern "C" dn_status dn_jacobi(double *u, double *work, int n, int m, int iters, double *max_change, void *stream)
+{
+    STCHK(jacobi_check(n, m, iters));
+    if (!u || !work) return fail(DN_EINVAL, "jacobi: NULL grid");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)n * m * sizeof(double);
+    if (iters == 0) {
+        if (max_change) HIPCHK(launch_zero_f32((float *)max_change, 2, s));  // a fill kernel, not a memset node
+        return DN_OK;
+    }
+    HIPCHK(hipMemcpyAsync(work, u, bytes, hipMemcpyDeviceToDevice, s));  // boundary values in both buffers
+    double *a = u, *b = work;
+    for (int it = 0; it < iters; ++it) {
+        const bool last = it + 1 == iters;
+        HIPCHK(launch_jacobi_step(a, b, n, m, last ? (unsigned long long *)max_change : nullptr, s));
+        std::swap(a, b);
+    }
+    if (a != u) HIPCHK(hipMemcpyAsync(u, a, bytes, hipMemcpyDeviceToDevice, s));
+    return DN_OK;
+}
+
+// The naive offload the paper's rule removes: the grid lives on the host and
+// crosses PCIe in both directions around every iteration, with a full
+// synchronisation each time.  Synchronous.
+extern "C" dn_status dn_jacobi_per_iteration(double *u_host, double *dev_a, double *dev_b, int n, int m, int iters,
+                                             double *max_change_host, void *stream)
+{
+    STCHK(jacobi_check(n, m, iters));
+    if (!u_host || !dev_a || !dev_b) return fail(DN_EINVAL, "jacobi: NULL buffer");
+    if (is_device_ptr(u_host)) return fail(DN_EINVAL, "jacobi per-iteration mode takes a host grid");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)n * m * sizeof(double);
+    unsigned long long *dmax = nullptr;
+    HIPCHK(hipMalloc(&dmax, sizeof(unsigned long long)));
+    dn_status rc = DN_OK;
+    unsigned long long hmax = 0;
+    for (int it = 0; it < iters && rc == DN_OK; ++it) {
+        if (hipMemcpyAsync(dev_a, u_host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(dev_b, dev_a, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            launch_jacobi_step(dev_a, dev_b, n, m, dmax, s) != hipSuccess ||
+            hipMemcpyAsync(u_host, dev_b, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&hmax, dmax, sizeof hmax, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = fail(DN_EHIP, "jacobi iteration %d failed", it);
+    }
+    (void)hipFree(dmax);
+    if (rc == DN_OK && max_change_host) {
+        double d;
+        memcpy(&d, &hmax, sizeof d);
+        *max_change_host = iters > 0 ? d : 0.0;
+    }
+    return rc;
+}
+
 // ---------------------------------------------------------------- detection
 
 static dn_status detect_check(int batch, int anchors, int classes, int h, int w)

@@ -11,6 +11,8 @@ import ctypes
 import os
 from typing import Optional, Sequence, Tuple
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdn.so")
 
@@ -86,6 +88,8 @@ SIGNATURES = {
     "dn_tile_count": (_i, []),
     "dn_tile_info": (_i, [_i, _ip, _ip, _ip, _ip, _ip]),
     "dn_mfma_peak": (_i, [_i, _i, ctypes.POINTER(ctypes.c_double)]),
+    "dn_jacobi": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_jacobi_per_iteration": (_i, [_vp, _vp, _vp, _i, _i, _i, _dp, _vp]),
     "dn_detect_workspace": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "dn_detect": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_float), _f, _f, _i, _vp, _sz, _vp, _vp,
                        _vp, _vp]),
@@ -161,6 +165,21 @@ def channel_pad(dtype: int, c: int) -> int:
 
 def tile_count() -> int:
     return LIB.dn_tile_count()
+
+
+def jacobi(u, work, n: int, m: int, iters: int, max_change=None, stream=None):
+    """Device-resident Jacobi iterations of the Laplace equation (see dn_jacobi)."""
+    check(LIB.dn_jacobi(ptr(u), ptr(work), n, m, iters, ptr(max_change), stream_handle(stream)))
+
+
+def jacobi_per_iteration(u_host: np.ndarray, dev_a, dev_b, iters: int, stream=None) -> float:
+    """The per-iteration-transfer variant on a host FP64 grid (updated in place);
+    returns the last iteration's max change."""
+    assert u_host.dtype == np.float64 and u_host.flags.c_contiguous
+    mc = ctypes.c_double()
+    check(LIB.dn_jacobi_per_iteration(u_host.ctypes.data, ptr(dev_a), ptr(dev_b), u_host.shape[0], u_host.shape[1],
+                                      iters, ctypes.byref(mc), stream_handle(stream)))
+    return mc.value
 
 
 def detect_workspace(batch: int, anchors: int, classes: int, h: int, w: int) -> int:
