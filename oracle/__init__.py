@@ -16,6 +16,8 @@ under ``tests/test_oracle_*.py``):
   conv2d, add_bias, batchnorm, leaky, maxpool, shortcut: pinned.
   net forward: composition of the pinned layers; pinned by layer-by-layer
   recomputation and by identity-unit constructions.
+  conv2d_backward_data, maxpool_backward (the image-edit gradient): pinned by
+  central finite differences of the forward definitions (tests/test_oracle_backward.py).
   detect (``detect.py``, region decode + per-class NMS, FP32 like the device
   kernels): pinned by hand-computed boxes, closed-form IoUs, and brute-force
   checks of the suppression invariants.
@@ -61,8 +63,11 @@ def _load(path: str = None):
             lib.oracle_leaky.argtypes = [dp, ctypes.c_long, ctypes.c_double]
             lib.oracle_maxpool.argtypes = [dp, i, i, i, i, i, i, dp]
             lib.oracle_shortcut.argtypes = [dp, dp, ctypes.c_long]
+            lib.oracle_conv2d_backward_data.argtypes = [dp, i, i, i, i, dp, i, i, i, i, i, i, i, dp]
+            lib.oracle_maxpool_backward.argtypes = [dp, i, i, i, i, i, i, dp, dp]
             for f in (lib.oracle_conv2d, lib.oracle_add_bias, lib.oracle_batchnorm,
-                      lib.oracle_leaky, lib.oracle_maxpool, lib.oracle_shortcut):
+                      lib.oracle_leaky, lib.oracle_maxpool, lib.oracle_shortcut,
+                      lib.oracle_conv2d_backward_data, lib.oracle_maxpool_backward):
                 f.restype = None
             _lib = lib
     return _lib
@@ -127,6 +132,27 @@ def shortcut(y, x) -> np.ndarray:
         raise ValueError("shortcut shape mismatch %s vs %s" % (y.shape, x.shape))
     _load().oracle_shortcut(_p(y), _p(x), y.size)
     return y
+
+
+def conv2d_backward_data(dy, w, stride: int, pad: int, h: int, wd: int) -> np.ndarray:
+    """Gradient of conv2d with respect to its input: dy [N,K,Ho,Wo], w [K,C,R,S] -> [N,C,h,wd]."""
+    dy, w = _f64(dy), _f64(w)
+    n, k, ho, wo = dy.shape
+    k2, c, r, s = w.shape
+    if k != k2:
+        raise ValueError("channel mismatch %d vs %d" % (k, k2))
+    dx = np.empty((n, c, h, wd), np.float64)
+    _load().oracle_conv2d_backward_data(_p(dy), n, k, ho, wo, _p(w), c, r, s, stride, pad, h, wd, _p(dx))
+    return dx
+
+
+def maxpool_backward(x, size: int, stride: int, dy) -> np.ndarray:
+    """Gradient of maxpool with respect to its input (first maximal element of each window)."""
+    x, dy = _f64(x), _f64(dy)
+    n, c, h, w = x.shape
+    dx = np.empty_like(x)
+    _load().oracle_maxpool_backward(_p(x), n, c, h, w, size, stride, _p(dy), _p(dx))
+    return dx
 
 
 class use_library:

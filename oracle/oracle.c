@@ -124,3 +124,65 @@ void oracle_shortcut(double *y, const double *x, long count)
     for (long i = 0; i < count; ++i)
         y[i] += x[i];
 }
+
+/* Backward of the convolution with respect to its input (the gradient the
+   image-edit program propagates to the image): for every output position and
+   tap, dx[n,c,i*stride-pad+r, j*stride-pad+s] += dy[n,k,i,j] * w[k,c,r,s];
+   taps outside the input contribute nothing.  dx is [n,c,h,wd], zeroed here. */
+void oracle_conv2d_backward_data(const double *dy, int n, int k, int ho, int wo,
+                                 const double *w, int c, int r, int s, int stride, int pad,
+                                 int h, int wd, double *dx)
+{
+    for (long t = 0; t < (long)n * c * h * wd; ++t)
+        dx[t] = 0.0;
+    for (int in = 0; in < n; ++in)
+        for (int ik = 0; ik < k; ++ik)
+            for (int i = 0; i < ho; ++i)
+                for (int j = 0; j < wo; ++j) {
+                    const double g = dy[((size_t)(in * k + ik) * ho + i) * wo + j];
+                    for (int ic = 0; ic < c; ++ic)
+                        for (int u = 0; u < r; ++u)
+                            for (int v = 0; v < s; ++v) {
+                                const int yy = i * stride - pad + u;
+                                const int xx = j * stride - pad + v;
+                                if (yy < 0 || yy >= h || xx < 0 || xx >= wd)
+                                    continue;
+                                dx[((size_t)(in * c + ic) * h + yy) * wd + xx] +=
+                                    g * w[(((size_t)ik * c + ic) * r + u) * s + v];
+                            }
+                }
+}
+
+/* Backward of max pooling: every output window hands its gradient to the
+   first maximal input of the window (row-major order inside the window, the
+   same strict comparison as the forward); dx is [n,c,h,w], zeroed here. */
+void oracle_maxpool_backward(const double *x, int n, int c, int h, int w,
+                             int size, int stride, const double *dy, double *dx)
+{
+    const int ho = (h - 1) / stride + 1;
+    const int wo = (w - 1) / stride + 1;
+    const int off = (size - 1) / 2;
+    for (long t = 0; t < (long)n * c * h * w; ++t)
+        dx[t] = 0.0;
+    for (int in = 0; in < n; ++in)
+        for (int ic = 0; ic < c; ++ic)
+            for (int i = 0; i < ho; ++i)
+                for (int j = 0; j < wo; ++j) {
+                    double m = -INFINITY;
+                    long arg = -1;
+                    for (int u = 0; u < size; ++u)
+                        for (int v = 0; v < size; ++v) {
+                            const int yy = i * stride - off + u;
+                            const int xx = j * stride - off + v;
+                            if (yy < 0 || yy >= h || xx < 0 || xx >= w)
+                                continue;
+                            const long q = ((long)(in * c + ic) * h + yy) * w + xx;
+                            if (x[q] > m) {
+                                m = x[q];
+                                arg = q;
+                            }
+                        }
+                    if (arg >= 0)
+                        dx[arg] += dy[((size_t)(in * c + ic) * ho + i) * wo + j];
+                }
+}
