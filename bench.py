@@ -271,6 +271,8 @@ def main():
     ap.add_argument("--pmc-driver", action="store_true",
                     help="run only the dominant conv kernel (5 launches) and a 256 MiB device copy, "
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--nightmare-driver", action="store_true",
+                    help="run only 5 image-modification steps (BF16, batch 64, 416x416), for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print a markdown summary of a rocprofv3 --kernel-trace CSV and exit (no GPU)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER"),
@@ -309,6 +311,14 @@ def main():
     x = torch.from_numpy(synth.make_input(net, B, synth.SEED_PLAIN).astype(np.float32)).cuda()
     stream = torch.cuda.Stream()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    if args.nightmare_driver:
+        n5, a5 = build_net(dn, torch, net, dn.BF16, B, H, W, params, use_graph=False, tune=False)
+        for _ in range(6):
+            n5.nightmare(len(net.layers) - 1, x, B, H, W, 0.01, 1, stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"nightmare_driver": True, "steps": 6, "batch": B}))
+        return
 
     # ---------------- headline: BF16 batch 64, graph-captured forward
     log("[bench] building BF16 b64 net + autotune")
@@ -474,6 +484,28 @@ def main():
                                        "algorithmic_bytes_per_iteration": jbytes}})
         log("[bench] jacobi: resident %.4f ms/iter, per-iteration transfer %.3f ms/iter" % (ms_res, ms_pl))
         del uj, wj, uh
+
+        # Image modification (the workload's second program): one gradient-ascent
+        # step on the energy of the last layer = unfused forward keeping every
+        # layer output + backward to the image + update, batch 64 at 416x416
+        fl_all = sum(v[0] for v in flops.values())
+        for name, dt in (("bf16", dn.BF16), ("f32", dn.F32)):
+            log("[bench] nightmare %s b64" % name)
+            n5, a5 = build_net(dn, torch, net, dt, B, H, W, params, use_graph=False, tune=False)
+            xn = x.clone()
+            last = len(net.layers) - 1
+            run = lambda: n5.nightmare(last, xn, B, H, W, 0.01, 1, stream)
+            with torch.cuda.stream(stream):
+                wn, pn = time_steps(torch, run, 5, 1, stream)
+            ms = wn * 1e3 / len(pn)
+            secondary.append({"workload": "image modification, 9-layer %s b64 416x416: gradient ascent on the last "
+                                          "layer's energy (forward keeping every output + backward to the image + update)" % name,
+                              "images_per_s": B * len(pn) / wn, "ms_per_step": ms,
+                              "conv_tflops": 2 * fl_all / (ms * 1e-3) / 1e12,
+                              "conv_pct_peak": 100.0 * 2 * fl_all / (ms * 1e-3) / PEAK[name]})
+            log("[bench] nightmare %s: %.3f ms per step" % (name, ms))
+            n5.close()
+            del a5, xn
 
         # FP32 plain path, batch 1: resident (graph) vs per-layer transfers
         x1 = x[:1].contiguous()

@@ -59,7 +59,8 @@ typedef enum dn_act { DN_ACT_LINEAR = 0, DN_ACT_LEAKY = 1 } dn_act;
  *   DN_MAXPOOL:  ksize = window, stride; -inf outside the input; output side
  *                (H - 1) / stride + 1; window starts at i*stride - (ksize-1)/2.
  *   DN_SHORTCUT: src = absolute index of an earlier layer; output =
- *                act(previous layer's output + layer src's output), shapes equal. */
+ *                previous layer's output + layer src's output, shapes equal;
+ *                activation must be DN_ACT_LINEAR (else DN_EUNSUPPORTED). */
 typedef struct dn_layer_desc {
     int kind;
     int cout, ksize, stride, pad;
@@ -217,6 +218,67 @@ dn_status dn_ingest(int dtype, int batch, int c, int h, int w, const float *x, f
 /* NHWC storage dtype (padded channels) -> NCHW FP32 (device). */
 dn_status dn_egress(int dtype, int batch, int c, int h, int w, const void *x, float scale,
                     float *y, void *stream);
+
+/* ---- backward pass to the input image: the image-modification program the
+ * paper ran beside detection (Sec. 5.1.1), which ascends the gradient of a
+ * layer's activation energy with respect to the input image.  The paper does
+ * not describe it; the definitions here are the plain derivatives of the
+ * forward layers above.  F32 and BF16 only (else DN_EUNSUPPORTED); the
+ * gradients have the storage dtype and the NHWC padded layout of the
+ * activations they belong to, with FP32 accumulation.
+ *
+ * Backward-data conv of a forward conv `d` (unfused: pool = residual =
+ * input_nchw = 0, pad <= ksize - 1):
+ *   dx[n,c,p,q] = sum over k,r,s with p = i*stride - pad + r, q = j*stride - pad + s
+ *                 of dy[n,k,i,j] * w'[k,c,r,s],  w' = w * gamma[k] / sqrt(var[k] + eps)
+ * (w' = w without BN).  It runs as a stride-1 forward conv over dy (spread
+ * onto the stride-1 grid with zeros when stride > 1) with channels swapped,
+ * the filter flipped and pad ksize - 1 - pad.  dy: NHWC [batch][Ho][Wo][cout
+ * padded]; dx: NHWC [batch][in_h][in_w][in_c padded]; accumulate = 1 adds
+ * the result to dx (dx then also is read).  The workspace (device, caller
+ * owned) holds split-K partials and the spread gradient. */
+dn_status dn_conv_backward_sizes(const dn_conv_desc *d, size_t *w_bytes, size_t *vec_bytes, size_t *ws_bytes);
+/* FP64 BN scale fold, flip, transpose, round and pack of the host weights w
+ * [cout][in_c][k][k] (BN arrays all present or all NULL) into caller device
+ * buffers: w_packed (w_bytes), zero_bias and unit_scale (vec_bytes each).
+ * Synchronous on `stream`. */
+dn_status dn_conv_pack_backward(const dn_conv_desc *d, const double *w, const double *mean,
+                                const double *var, const double *gamma, double eps, void *w_packed,
+                                float *zero_bias, float *unit_scale, void *stream);
+dn_status dn_conv_backward_data(const dn_conv_desc *d, const void *dy, const void *w_packed,
+                                const float *zero_bias, const float *unit_scale, int accumulate, void *dx,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* Max-pool gradient: every window hands its gradient to its first maximal
+ * element in row-major window order (the forward's comparison), elements
+ * outside the input never win.  x: the pool's forward input; dy: gradient of
+ * its output; dx (+)= result (accumulate = 1 adds).  NHWC device tensors. */
+dn_status dn_maxpool_backward(const dn_pool_desc *d, const void *x, const void *dy, int accumulate,
+                              void *dx, void *stream);
+
+/* Leaky-rectifier gradient over `count` padded elements: dx = dy where the
+ * layer's forward output a > 0, else dy * slope (0 <= slope <= 1, so a has the
+ * sign of the pre-activation).  dx may be dy. */
+dn_status dn_leaky_backward(int dtype, size_t count, const void *a, const void *dy, float slope, void *dx,
+                            void *stream);
+
+/* Gradient with respect to the input image of E = 1/2 * sum of squares of
+ * layer `layer`'s output over the batch.  x, grad: device NCHW FP32
+ * [batch][in_c][h][w].  Runs the forward up to `layer` unfused, keeping every
+ * layer output, then each layer's backward in reverse order (gradients of a
+ * shortcut's two inputs add up).  Needs every conv's weights loaded
+ * (DN_ESTATE).  The library keeps one device buffer per net for this pass,
+ * grown on demand (hipMalloc outside any capture) and freed by
+ * dn_net_destroy; calls on one net must not overlap.  Enqueue only. */
+dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
+                            void *stream);
+
+/* `iters` steps of gradient ascent on E with respect to the image, in place:
+ * x = clamp(x + rate * g / mean|g|, 0, 1), mean |g| per image (a step of
+ * `rate` in the mean absolute sense).  Same buffers and rules as
+ * dn_input_gradient; no host round-trip between iterations. */
+dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, int h, int w, float rate, int iters,
+                       void *stream);
 
 /* ---- Jacobi iteration for the Laplace equation: the second program the
  * paper's transfer rule sped up (Sec. 4, the paragraph before Sec. 5).

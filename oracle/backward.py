@@ -25,9 +25,15 @@ back through the layers 0..L one at a time:
 One ascent step: x' = clip(x + rate * g / mean|g|, 0, 1), mean |g| taken per
 image (left unchanged where g is zero).
 
+``input_gradient_stored`` is the same gradient for the BF16 path's
+definition (stored operands rounded to BF16), so that every branch is taken
+on the same stored values as on the device.
+
 Pins: tests/test_oracle_backward.py checks every piece against central
 finite differences of the forward definitions and the adjoint identity of the
-convolution, and the step against its closed form on an identity network.
+convolution, the step against its closed form on an identity network, the
+stored-operand variant against the plain one when nothing is rounded, and the
+BF16 rounding against hand-worked values.
 """
 from __future__ import annotations
 
@@ -37,8 +43,83 @@ import numpy as np
 
 from synth import CONV, LEAKY, MAXPOOL, SHORTCUT, ConvParams, Net
 
-from . import add_bias, batchnorm, conv2d, conv2d_backward_data, maxpool_backward
+from . import add_bias, batchnorm, conv2d, conv2d_backward_data, maxpool, maxpool_backward
 from .net import forward
+
+
+def round_bf16(a) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as FP64: the
+    8-bit-significand storage format of the BF16 path."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_f32(a) -> np.ndarray:
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _forward_stored(net: Net, params, x: np.ndarray, layer: int, q, qb):
+    """Forward up to ``layer`` with every stored operand in a storage format:
+    the input image, the BN-folded weights (fold in FP64, then q) and every
+    layer output pass through q; the folded bias through qb; arithmetic is FP64.
+    Returns (layer inputs, layer outputs, stored weights)."""
+    cur = q(x)
+    ins, outs, wq = [], [], {}
+    for i in range(layer + 1):
+        L = net.layers[i]
+        ins.append(cur)
+        if L.kind == CONV:
+            p = params[i]
+            w = np.asarray(p.w, np.float64)
+            b = np.asarray(p.bias, np.float64)
+            if L.batchnorm:
+                sc = np.asarray(p.gamma, np.float64) / np.sqrt(np.asarray(p.var, np.float64) + net.bn_eps)
+                w = w * sc[:, None, None, None]
+                b = (b - np.asarray(p.mean, np.float64)) * sc + np.asarray(p.beta, np.float64)
+            wq[i] = q(w)
+            z = add_bias(conv2d(cur, wq[i], L.stride, L.pad), qb(b))
+            if L.activation == LEAKY:
+                z = np.where(z > 0.0, z, z * net.leaky_slope)
+            cur = q(z)
+        elif L.kind == MAXPOOL:
+            cur = maxpool(cur, L.ksize, L.stride)
+        elif L.kind == SHORTCUT:
+            cur = q(outs[i - 1] + outs[L.src])
+        else:
+            raise ValueError("unknown layer kind %r" % (L.kind,))
+        outs.append(cur)
+    return ins, outs, wq
+
+
+def input_gradient_stored(net: Net, params, x: np.ndarray, layer: int, q=round_bf16, qb=round_f32) -> np.ndarray:
+    """dE/dx of the network whose stored operands are in the format q (the
+    BF16 path's definition: BF16 image, folded weights and activations, FP32
+    bias).  Every branch (leaky sign, first maximum of a pooling window) is
+    taken on the stored activations, as the device takes it; the gradient
+    arithmetic is FP64 with the stored weights."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    ins, outs, wq = _forward_stored(net, params, x, layer, q, qb)
+    grads: List[Optional[np.ndarray]] = [None] * (layer + 2)
+
+    def add(v: int, g: np.ndarray) -> None:
+        grads[v] = g if grads[v] is None else grads[v] + g
+
+    grads[layer + 1] = outs[layer].copy()
+    for i in range(layer, -1, -1):
+        L = net.layers[i]
+        gy = grads[i + 1]
+        if L.kind == CONV:
+            if L.activation == LEAKY:
+                gy = gy * np.where(outs[i] > 0.0, 1.0, net.leaky_slope)
+            add(i, conv2d_backward_data(gy, wq[i], L.stride, L.pad, ins[i].shape[2], ins[i].shape[3]))
+        elif L.kind == MAXPOOL:
+            add(i, maxpool_backward(ins[i], L.ksize, L.stride, gy))
+        else:
+            add(i, gy)
+            add(L.src + 1, gy)
+    return grads[0]
 
 
 def energy(net: Net, params: List[Optional[ConvParams]], x: np.ndarray, layer: int) -> float:

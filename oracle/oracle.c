@@ -135,12 +135,14 @@ void oracle_conv2d_backward_data(const double *dy, int n, int k, int ho, int wo,
 {
     for (long t = 0; t < (long)n * c * h * wd; ++t)
         dx[t] = 0.0;
+    /* each (image, input channel) plane is written by one thread only */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int in = 0; in < n; ++in)
-        for (int ik = 0; ik < k; ++ik)
-            for (int i = 0; i < ho; ++i)
-                for (int j = 0; j < wo; ++j) {
-                    const double g = dy[((size_t)(in * k + ik) * ho + i) * wo + j];
-                    for (int ic = 0; ic < c; ++ic)
+        for (int ic = 0; ic < c; ++ic)
+            for (int ik = 0; ik < k; ++ik)
+                for (int i = 0; i < ho; ++i)
+                    for (int j = 0; j < wo; ++j) {
+                        const double g = dy[((size_t)(in * k + ik) * ho + i) * wo + j];
                         for (int u = 0; u < r; ++u)
                             for (int v = 0; v < s; ++v) {
                                 const int yy = i * stride - pad + u;
@@ -150,7 +152,7 @@ void oracle_conv2d_backward_data(const double *dy, int n, int k, int ho, int wo,
                                 dx[((size_t)(in * c + ic) * h + yy) * wd + xx] +=
                                     g * w[(((size_t)ik * c + ic) * r + u) * s + v];
                             }
-                }
+                    }
 }
 
 /* Backward of max pooling: every output window hands its gradient to the

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdn.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["conv.hip", "aux.hip", "detect.hip", "jacobi.hip", "runtime.cpp"]
+SOURCES = ["conv.hip", "aux.hip", "backward.hip", "detect.hip", "jacobi.hip", "runtime.cpp"]
 ARCH = "gfx950"
 
 

@@ -5,61 +5,9 @@
 // calibration.  All activations are NHWC with 16-byte padded channels; every
 // kernel moves whole 16-byte segments where the layout allows it.
 #include "dn_kernels.h"
+#include "seg.h"
 
 namespace dnk {
-
-// ---------------------------------------------------------------- conversions
-// (same rounding as the conv epilogue: nearest even; FP8 saturates at +-448)
-
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    return __builtin_bit_cast(uint16_t, (__bf16)f);  // v_cvt_pk_bf16_f32: round to nearest even
-}
-__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
-__device__ __forceinline__ uint32_t f2e4m3(float f)
-{
-    f = fminf(fmaxf(f, -448.0f), 448.0f);
-    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(f, f, 0, false) & 0xFFu;
-}
-__device__ __forceinline__ float e4m32f(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
-
-// Decode / encode one 16-byte segment (4, 8 or 16 elements) to/from floats.
-template <int DT> struct Seg;
-template <> struct Seg<F32> {
-    static constexpr int N = 4;
-    __device__ static void dec(uint4 u, float *f) { f[0] = __uint_as_float(u.x); f[1] = __uint_as_float(u.y); f[2] = __uint_as_float(u.z); f[3] = __uint_as_float(u.w); }
-    __device__ static uint4 enc(const float *f) { return make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3])); }
-};
-template <> struct Seg<BF16> {
-    static constexpr int N = 8;
-    __device__ static void dec(uint4 u, float *f)
-    {
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-        for (int i = 0; i < 4; ++i) { f[2 * i] = bf2f(w[i] & 0xFFFFu); f[2 * i + 1] = bf2f(w[i] >> 16); }
-    }
-    __device__ static uint4 enc(const float *f)
-    {
-        uint32_t w[4];
-        for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
-        return make_uint4(w[0], w[1], w[2], w[3]);
-    }
-};
-template <> struct Seg<FP8> {
-    static constexpr int N = 16;
-    __device__ static void dec(uint4 u, float *f)
-    {
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) f[4 * i + j] = e4m32f((w[i] >> (8 * j)) & 0xFFu);
-    }
-    __device__ static uint4 enc(const float *f)
-    {
-        uint32_t w[4];
-        for (int i = 0; i < 4; ++i)
-            w[i] = f2e4m3(f[4 * i]) | (f2e4m3(f[4 * i + 1]) << 8) | (f2e4m3(f[4 * i + 2]) << 16) | (f2e4m3(f[4 * i + 3]) << 24);
-        return make_uint4(w[0], w[1], w[2], w[3]);
-    }
-};
 
 // ---------------------------------------------------------------- fold + pack
 // One block per padded output channel.  FP64: scale = gamma / sqrt(var + eps),
@@ -68,10 +16,15 @@ template <> struct Seg<FP8> {
 // CB = kblock_ch(dt, cin_p, R*S) (compact: k = r*16 + s*CP + c,
 // CP = first_cp(cin)),
 // zeros in every padding.
+// Mode 2 packs the backward-data conv of a forward conv (stride 1 over the
+// output gradient): here cout / cin are the forward conv's cin / cout, the
+// raw array is the forward [cin][cout][R][S] one, and the packed weight is
+// w'[co][c][r][s] = w[c][co][R-1-r][S-1-s] * scale[c] with the forward BN
+// scale of channel c (FP64), bias 0.
 // FP8 rows get scale s = max|w'| / 448 and store e4m3(w' / s).
 
 template <int DT>
-__global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, const double *bias, const double *mean,
+__global__ void __launch_bounds__(256) fold_pack(int mode, const double *w, const double *bias, const double *mean,
                                                  const double *var, const double *gamma, const double *beta,
                                                  double eps, int has_bn, int cout, int cin, int R, int S,
                                                  int cin_p, int k_pad, void *wout, float *bout, float *sout)
@@ -79,7 +32,7 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
     const int co = blockIdx.x;
     const int RS = R * S;
     double sc = 1.0, bb = 0.0;
-    if (co < cout) {
+    if (co < cout && mode != 2) {
         if (has_bn) {
             sc = gamma[co] / sqrt(var[co] + eps);
             bb = (bias[co] - mean[co]) * sc + beta[co];
@@ -89,7 +42,7 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
     }
     auto wval = [&](int k) -> double {
         int c, r, s;
-        if (compact) {  // k = r*16 + s*CP + c
+        if (mode == 1) {  // k = r*16 + s*CP + c
             const int cp = first_cp(cin);
             r = k / 16;
             const int e = k - r * 16;
@@ -103,6 +56,10 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
             if (co >= cout || c >= cin) return 0.0;
             r = tap / S;
             s = tap - r * S;
+        }
+        if (mode == 2) {
+            const double g = has_bn ? gamma[c] / sqrt(var[c] + eps) : 1.0;
+            return w[(((size_t)c * cout + co) * R + (R - 1 - r)) * S + (S - 1 - s)] * g;
         }
         return w[(((size_t)co * cin + c) * R + r) * S + s] * sc;
     };
@@ -132,16 +89,16 @@ __global__ void __launch_bounds__(256) fold_pack(int compact, const double *w, c
     }
 }
 
-hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
+hipError_t launch_fold_pack(int dt, int mode, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta, double eps,
                             int has_bn, int cout, int cin, int R, int S, int cin_p, int k_pad,
                             int cout_p, void *wout, float *bout, float *sout, hipStream_t s)
 {
     dim3 g(cout_p), b(256);
     switch (dt) {
-    case F32: hipLaunchKernelGGL(fold_pack<F32>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
-    case BF16: hipLaunchKernelGGL(fold_pack<BF16>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
-    case FP8: hipLaunchKernelGGL(fold_pack<FP8>, g, b, 0, s, compact, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case F32: hipLaunchKernelGGL(fold_pack<F32>, g, b, 0, s, mode, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case BF16: hipLaunchKernelGGL(fold_pack<BF16>, g, b, 0, s, mode, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
+    case FP8: hipLaunchKernelGGL(fold_pack<FP8>, g, b, 0, s, mode, w, bias, mean, var, gamma, beta, eps, has_bn, cout, cin, R, S, cin_p, k_pad, wout, bout, sout); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -96,9 +96,10 @@ TileCfg tile_cfg(int i);
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
 
-// compact = 1 packs k = r*16 + s*first_cp(cin) + c (first-layer kernel; cin_p unused),
-// else k = (r*S + s)*cin_p + c.
-hipError_t launch_fold_pack(int dt, int compact, const double *w, const double *bias, const double *mean,
+// mode 0 packs k = (cb*R*S + r*S + s)*CB + ci; mode 1 packs k = r*16 + s*first_cp(cin) + c
+// (first-layer kernel; cin_p unused); mode 2 packs the transposed, flipped
+// weights of a forward conv's backward-data conv (cout, cin are the forward cin, cout).
+hipError_t launch_fold_pack(int dt, int mode, const double *w, const double *bias, const double *mean,
                             const double *var, const double *gamma, const double *beta,
                             double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,
                             int k_pad, int cout_p, void *wout, float *bout, float *sout,
@@ -114,6 +115,20 @@ hipError_t launch_add(int dt, const void *a, float sa, const void *b, float sb, 
 // amax of |x| over `count` FP32 values, max-combined into *out (caller zeroes *out).
 hipError_t launch_amax(const float *x, size_t count, float *out, hipStream_t s);
 hipError_t launch_zero_f32(float *p, size_t count, hipStream_t s);
+// Backward pass to the input (backward.hip; F32 and BF16).
+// dx = dy * (a > 0 ? 1 : slope) over `count` padded elements (dx may be dy).
+hipError_t launch_leaky_bwd(int dt, const void *a, const void *dy, void *dx, float slope, size_t count, hipStream_t s);
+// Max-pool gradient (first maximal element of each window); accumulate = 1 adds to dx.
+// mask >= 0 also multiplies by the leaky gradient of x (1 where x > 0, else mask).
+hipError_t launch_maxpool_bwd(int dt, const void *x, const void *dy, void *dx, int n, int h, int w, int cp, int size,
+                              int stride, int ho, int wo, int accumulate, float mask, hipStream_t s);
+// z[n][hz][wz][cp] = dy[n][i/stride][j/stride] where stride divides i and j, else 0.
+hipError_t launch_dilate(int dt, const void *dy, void *z, int n, int ho, int wo, int cp, int hz, int wz, int stride,
+                         hipStream_t s);
+// Per image: m = mean |g|, then x = clamp(x + rate * g / m, 0, 1) (FP32 NCHW);
+// scratch: ascend_scratch_bytes(n) bytes (m first, n doubles).
+size_t ascend_scratch_bytes(int n);
+hipError_t launch_ascend(float *x, const float *g, double *scratch, int n, size_t per_image, float rate, hipStream_t s);
 // Region decode + per-class NMS (detect.hip).
 constexpr int DETECT_MAX_ANCHORS = 16;
 constexpr int DETECT_MAX_BOXES = 4096;  // H * W * A per image (sorted in LDS)

@@ -72,6 +72,11 @@ struct ConvWeights {
     std::vector<unsigned char> host_w;  // per-layer mode: host copy of the packed weights
     std::vector<float> host_bias, host_wscale;
     void *pinned = nullptr;   // pinned staging of host_w|bias|wscale (per-layer mode)
+    // backward-data conv (F32 / BF16 nets): transposed, flipped, BN-scaled
+    // weights [cin_p][kb_pad], a zero bias and unit scales of cin_p entries
+    void *wb = nullptr;
+    float *bzero = nullptr, *bscale = nullptr;
+    int kb_pad = 0;
     size_t wbytes = 0;
     bool loaded = false;
 };
@@ -129,6 +134,8 @@ struct dn_net {
     std::map<GraphKey, GraphPair> graphs;
     std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
+    void *bwd_buf = nullptr;                // library-owned buffer of the input-gradient pass
+    size_t bwd_bytes = 0;
     std::mutex mu;
 };
 
@@ -562,8 +569,8 @@ extern "C" dn_status dn_net_create(const dn_layer_desc *layers, int n, const dn_
         } else if (d.kind == DN_SHORTCUT) {
             if (d.src < 0 || d.src >= i)
                 return fail(DN_EINVAL, "shortcut layer %d: src %d must name an earlier layer", i, d.src);
-            if (d.activation != DN_ACT_LINEAR && d.activation != DN_ACT_LEAKY)
-                return fail(DN_EINVAL, "shortcut layer %d: unknown activation", i);
+            if (d.activation != DN_ACT_LINEAR)
+                return fail(DN_EUNSUPPORTED, "shortcut layer %d: only a linear shortcut is supported", i);
         } else {
             return fail(DN_EINVAL, "layer %d: unknown kind %d", i, d.kind);
         }
@@ -603,6 +610,9 @@ static void free_weights(ConvWeights &cw)
     if (cw.bias32) (void)hipFree(cw.bias32);
     if (cw.wscale32) (void)hipFree(cw.wscale32);
     if (cw.pinned) (void)hipHostFree(cw.pinned);
+    if (cw.wb) (void)hipFree(cw.wb);
+    if (cw.bzero) (void)hipFree(cw.bzero);
+    if (cw.bscale) (void)hipFree(cw.bscale);
     cw = ConvWeights();
 }
 
@@ -616,6 +626,7 @@ extern "C" void dn_net_destroy(dn_net *net)
     for (auto &kv : net->host_vals)
         for (unsigned char *b : kv.second) (void)hipHostFree(b);
     if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
+    if (net->bwd_buf) (void)hipFree(net->bwd_buf);
     delete net;
 }
 
@@ -675,6 +686,26 @@ static dn_status pack_to(dn_net *net, int layer, int dt, const double *dw, const
     return DN_OK;
 }
 
+// Backward-data weights of conv layer `layer`: the conv with the forward's
+// input and output channels swapped, filter flipped, BN scale folded in.
+static dn_status pack_backward(dn_net *net, int layer, const double *dw, const double *db, const double *dm,
+                               const double *dv, const double *dg, const double *dbe, int has_bn, hipStream_t st)
+{
+    ConvWeights &cw = net->cw[layer];
+    const dn_layer_desc &d = net->L[layer];
+    const int dt = net->o.dtype;
+    const int cin_p = cpad(dt, d.cout), cout_p = cpad(dt, cw.cin);
+    const int K = d.ksize * d.ksize * cin_p;
+    const int k_pad = (K + bk_el(dt) - 1) / bk_el(dt) * bk_el(dt);
+    HIPCHK(hipMalloc(&cw.wb, (size_t)cout_p * k_pad * esize(dt)));
+    HIPCHK(hipMalloc((void **)&cw.bzero, cout_p * sizeof(float)));
+    HIPCHK(hipMalloc((void **)&cw.bscale, cout_p * sizeof(float)));
+    HIPCHK(launch_fold_pack(dt, 2, dw, db, dm, dv, dg, dbe, net->o.bn_eps, has_bn, cw.cin, d.cout, d.ksize, d.ksize,
+                            cin_p, k_pad, cout_p, cw.wb, cw.bzero, cw.bscale, st));
+    cw.kb_pad = k_pad;
+    return DN_OK;
+}
+
 extern "C" dn_status dn_load_weights(dn_net *net, int layer, const double *w, const double *bias, const double *mean,
                                      const double *var, const double *gamma, const double *beta)
 {
@@ -710,6 +741,7 @@ extern "C" dn_status dn_load_weights(dn_net *net, int layer, const double *w, co
         rc = pack_to(net, layer, net->o.dtype, dw, db, dm, dv, dg, dbe, d.batchnorm, &cw.w, &cw.bias, &cw.wscale, st);
     if (rc == DN_OK && net->o.dtype == DN_FP8_E4M3)
         rc = pack_to(net, layer, F32, dw, db, dm, dv, dg, dbe, d.batchnorm, &cw.w32, &cw.bias32, &cw.wscale32, st);
+    if (rc == DN_OK && net->o.dtype != DN_FP8_E4M3) rc = pack_backward(net, layer, dw, db, dm, dv, dg, dbe, d.batchnorm, st);
     if (rc == DN_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(DN_EHIP, "weight fold/pack failed");
     (void)hipFree(dbuf);
     if (rc != DN_OK) {
@@ -1410,6 +1442,346 @@ extern "C" dn_status dn_egress(int dtype, int batch, int c, int h, int w, const 
     if (!x || !y || batch <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "egress: bad argument");
     HIPCHK(launch_egress(dtype, x, batch, c, h, w, cpad(dtype, c), dtype == DN_FP8_E4M3 ? scale : 1.0f, y,
                          (hipStream_t)stream));
+    return DN_OK;
+}
+
+// ---------------------------------------------------------------- backward to the input
+
+// The backward-data conv of forward conv `f`, as a forward conv over the
+// (spread, when f is strided) output gradient: in_c = f.cout, cout = f.in_c,
+// stride 1, pad k-1-pad, linear, bias 0.  hz x wz is its input size.
+static dn_status bwd_desc(const dn_conv_desc *f, int accumulate, dn_conv_desc *b, int *ho, int *wo, int *hz, int *wz)
+{
+    if (!f) return fail(DN_EINVAL, "conv desc is NULL");
+    if (f->dtype != DN_F32 && f->dtype != DN_BF16) return fail(DN_EUNSUPPORTED, "backward: F32 and BF16 only");
+    if (f->pool || f->residual || f->input_nchw)
+        return fail(DN_EUNSUPPORTED, "backward: the forward conv must be unfused (no pool, residual or NCHW input)");
+    if (f->batch <= 0 || f->in_h <= 0 || f->in_w <= 0 || f->in_c <= 0 || f->cout <= 0 || f->ksize <= 0 ||
+        f->stride <= 0 || f->pad < 0)
+        return fail(DN_EINVAL, "conv desc: non-positive size");
+    if (f->pad > f->ksize - 1) return fail(DN_EUNSUPPORTED, "backward: pad %d > ksize - 1", f->pad);
+    *ho = out_side_conv(f->in_h, f->ksize, f->stride, f->pad);
+    *wo = out_side_conv(f->in_w, f->ksize, f->stride, f->pad);
+    if (*ho <= 0 || *wo <= 0) return fail(DN_EINVAL, "conv desc: output is empty");
+    *hz = f->in_h + 2 * f->pad - f->ksize + 1;
+    *wz = f->in_w + 2 * f->pad - f->ksize + 1;
+    memset(b, 0, sizeof *b);
+    b->batch = f->batch; b->in_h = *hz; b->in_w = *wz; b->in_c = f->cout;
+    b->cout = f->in_c; b->ksize = f->ksize; b->stride = 1; b->pad = f->ksize - 1 - f->pad;
+    b->activation = DN_ACT_LINEAR; b->dtype = f->dtype; b->residual = accumulate ? 1 : 0;
+    b->in_scale = b->res_scale = b->out_scale = 1.0f;
+    b->tile = -1; b->splits = 0;
+    ConvArgs a;
+    STCHK(conv_geometry(b, &a, nullptr, nullptr, nullptr, nullptr, nullptr));
+    if (halo_ok(f->dtype, a)) b->tile = HALO_TILE;
+    return DN_OK;
+}
+
+// Scratch of a backward-data conv: split-K partials, then the spread gradient.
+static dn_status bwd_scratch(const dn_conv_desc *f, const dn_conv_desc *b, int hz, int wz, size_t *ws, size_t *z)
+{
+    size_t need = 0;
+    STCHK(conv_geometry(b, nullptr, nullptr, nullptr, nullptr, nullptr, &need));
+    *ws = align256(need);
+    *z = f->stride > 1 ? align256((size_t)f->batch * hz * wz * cpad(f->dtype, f->cout) * esize(f->dtype)) : 0;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_conv_backward_sizes(const dn_conv_desc *d, size_t *w_bytes, size_t *vec_bytes, size_t *ws_bytes)
+{
+    dn_conv_desc b;
+    int ho, wo, hz, wz;
+    STCHK(bwd_desc(d, 0, &b, &ho, &wo, &hz, &wz));
+    size_t ws = 0, z = 0;
+    STCHK(bwd_scratch(d, &b, hz, wz, &ws, &z));
+    if (w_bytes || vec_bytes) STCHK(conv_geometry(&b, nullptr, nullptr, nullptr, w_bytes, vec_bytes, nullptr));
+    if (ws_bytes) *ws_bytes = ws + z;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_conv_pack_backward(const dn_conv_desc *d, const double *w, const double *mean,
+                                           const double *var, const double *gamma, double eps, void *w_packed,
+                                           float *zero_bias, float *unit_scale, void *stream)
+{
+    dn_conv_desc b;
+    int ho, wo, hz, wz;
+    STCHK(bwd_desc(d, 0, &b, &ho, &wo, &hz, &wz));
+    size_t wb = 0;
+    STCHK(conv_geometry(&b, nullptr, nullptr, nullptr, &wb, nullptr, nullptr));
+    if (!w || !w_packed || !zero_bias || !unit_scale) return fail(DN_EINVAL, "backward pack: NULL pointer");
+    const bool any_bn = mean || var || gamma, all_bn = mean && var && gamma;
+    if (any_bn && !all_bn) return fail(DN_EINVAL, "backward pack: BN arrays must be all present or all NULL");
+    if (all_bn && !(eps > 0)) return fail(DN_EINVAL, "backward pack: eps must be > 0");
+    const int dt = d->dtype;
+    const int cin_p = cpad(dt, d->cout), cout_p = cpad(dt, d->in_c);
+    const int k_pad = (int)(wb / esize(dt) / cout_p);
+    const size_t nw = (size_t)d->cout * d->in_c * d->ksize * d->ksize, nv = d->cout;
+    hipStream_t s = (hipStream_t)stream;
+    double *buf = nullptr;
+    HIPCHK(hipMalloc(&buf, (nw + 3 * nv) * sizeof(double)));
+    double *dw = buf, *dm = buf + nw, *dv = dm + nv, *dg = dv + nv;
+    dn_status rc = DN_OK;
+    auto cp = [&](double *dst, const double *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = cp(dw, w, nw);
+    if (ok && all_bn) ok = cp(dm, mean, nv) && cp(dv, var, nv) && cp(dg, gamma, nv);
+    if (!ok) rc = fail(DN_EHIP, "backward pack upload failed");
+    if (rc == DN_OK && launch_fold_pack(dt, 2, dw, nullptr, dm, dv, dg, nullptr, eps, all_bn ? 1 : 0, d->in_c, d->cout,
+                                        d->ksize, d->ksize, cin_p, k_pad, cout_p, w_packed, zero_bias, unit_scale,
+                                        s) != hipSuccess)
+        rc = fail(DN_EHIP, "backward fold/pack launch failed");
+    if (hipStreamSynchronize(s) != hipSuccess && rc == DN_OK) rc = fail(DN_EHIP, "backward fold/pack failed");
+    (void)hipFree(buf);
+    return rc;
+}
+
+// Enqueue dx (+)= backward-data conv of dy, scratch = [split-K | spread gradient].
+static dn_status enqueue_conv_backward(const dn_conv_desc *f, const void *dy, const void *w_packed,
+                                       const float *zero_bias, const float *unit_scale, int accumulate, void *dx,
+                                       void *scratch, size_t scratch_bytes, hipStream_t s)
+{
+    dn_conv_desc b;
+    int ho, wo, hz, wz;
+    STCHK(bwd_desc(f, accumulate, &b, &ho, &wo, &hz, &wz));
+    size_t ws = 0, z = 0;
+    STCHK(bwd_scratch(f, &b, hz, wz, &ws, &z));
+    if (ws + z > 0 && (!scratch || scratch_bytes < ws + z))
+        return fail(DN_EINVAL, "conv backward: needs %zu workspace bytes (%zu given)", ws + z, scratch_bytes);
+    const void *src = dy;
+    if (f->stride > 1) {
+        void *zb = (char *)scratch + ws;
+        HIPCHK(launch_dilate(f->dtype, dy, zb, f->batch, ho, wo, cpad(f->dtype, f->cout), hz, wz, f->stride, s));
+        src = zb;
+    }
+    ConvArgs a;
+    int tile = 0, splits = 1;
+    STCHK(conv_geometry(&b, &a, &tile, &splits, nullptr, nullptr, nullptr));
+    a.x = src; a.w = w_packed; a.bias = zero_bias; a.wscale = unit_scale;
+    a.res = accumulate ? dx : nullptr;
+    a.y = dx;
+    a.partial = (float *)scratch;
+    HIPCHK(launch_conv(f->dtype, tile, a, s));
+    if (splits > 1) HIPCHK(launch_splitk_reduce(f->dtype, a, s));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_conv_backward_data(const dn_conv_desc *d, const void *dy, const void *w_packed,
+                                           const float *zero_bias, const float *unit_scale, int accumulate, void *dx,
+                                           void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!dy || !w_packed || !zero_bias || !unit_scale || !dx) return fail(DN_EINVAL, "conv backward: NULL pointer");
+    return enqueue_conv_backward(d, dy, w_packed, zero_bias, unit_scale, accumulate, dx, workspace, ws_bytes,
+                                 (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_maxpool_backward(const dn_pool_desc *d, const void *x, const void *dy, int accumulate,
+                                         void *dx, void *stream)
+{
+    if (!d || !x || !dy || !dx) return fail(DN_EINVAL, "maxpool backward: NULL argument");
+    if (d->dtype != DN_F32 && d->dtype != DN_BF16) return fail(DN_EUNSUPPORTED, "backward: F32 and BF16 only");
+    if (d->batch <= 0 || d->h <= 0 || d->w <= 0 || d->c <= 0 || d->size <= 0 || d->stride <= 0)
+        return fail(DN_EINVAL, "maxpool backward: non-positive size");
+    HIPCHK(launch_maxpool_bwd(d->dtype, x, dy, dx, d->batch, d->h, d->w, cpad(d->dtype, d->c), d->size, d->stride,
+                              out_side_pool(d->h, d->stride), out_side_pool(d->w, d->stride), accumulate ? 1 : 0,
+                              -1.0f, (hipStream_t)stream));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_leaky_backward(int dtype, size_t count, const void *a, const void *dy, float slope, void *dx,
+                                       void *stream)
+{
+    if (dtype != DN_F32 && dtype != DN_BF16) return fail(DN_EUNSUPPORTED, "backward: F32 and BF16 only");
+    if (!a || !dy || !dx) return fail(DN_EINVAL, "leaky backward: NULL argument");
+    if (count % seg_el(dtype)) return fail(DN_EINVAL, "leaky backward: count must be a multiple of %d", seg_el(dtype));
+    if (!(slope >= 0.0f && slope <= 1.0f)) return fail(DN_EINVAL, "leaky backward: slope must lie in [0, 1]");
+    HIPCHK(launch_leaky_bwd(dtype, a, dy, dx, slope, count, (hipStream_t)stream));
+    return DN_OK;
+}
+
+// The input-gradient pass of a net: the unfused forward up to layer `target`
+// keeping every layer output, then the layers' backward in reverse order.
+struct BwdPlan {
+    Plan p;                          // unfused forward plan; vals[].off = forward outputs
+    int nops = 0, seed = 0;          // ops 0..nops-1 run; seed = value whose gradient starts the pass
+    std::vector<size_t> goff, gbytes;  // gradient of each value 0..seed
+    std::vector<dn_conv_desc> fwd;   // per op: the forward conv as a standalone desc (convs only)
+    std::vector<char> pool_leaky;    // per op: this pool applies the leaky gradient of its input's producer
+    size_t bws_off = 0, bws_bytes = 0;  // backward conv scratch
+    size_t gin_off = 0, mabs_off = 0;   // NCHW FP32 input gradient, per-image mean |g|
+    size_t total = 0;
+};
+
+static dn_status make_bwd_plan(const dn_net *net, int target, int batch, int h, int w, BwdPlan *out)
+{
+    const int dt = net->o.dtype;
+    if (dt != DN_F32 && dt != DN_BF16) return fail(DN_EUNSUPPORTED, "input gradient: F32 and BF16 nets only");
+    if (target < 0 || target >= (int)net->L.size()) return fail(DN_EINVAL, "layer %d out of range", target);
+    BwdPlan b;
+    STCHK(make_plan(net, dt, DN_MODE_PER_LAYER, batch, h, w, &b.p));
+    Plan &p = b.p;
+    b.nops = target + 1;  // unfused: op i computes layer i
+    b.seed = target + 1;
+    size_t off = 0;
+    for (int v = 0; v <= b.seed; ++v) {
+        p.vals[v].off = off;
+        off += p.vals[v].bytes;
+    }
+    p.ws_off = align256(off);
+    off = p.ws_off + align256(p.ws_bytes);
+    b.goff.resize(b.seed + 1);
+    b.gbytes.resize(b.seed + 1);
+    for (int v = 0; v <= b.seed; ++v) {
+        const Value &vv = p.vals[v];
+        b.gbytes[v] = align256((size_t)batch * vv.h * vv.w * vv.cp * esize(dt));
+        b.goff[v] = off;
+        off += b.gbytes[v];
+    }
+    b.fwd.resize(b.nops);
+    // a pool whose input is a leaky conv's output read by nothing else applies
+    // that conv's leaky gradient itself (the conv op then skips its pass)
+    std::vector<int> readers(b.seed + 1, 0);
+    for (int k = 0; k < b.nops; ++k) {
+        readers[p.ops[k].in]++;
+        if (p.ops[k].in2 >= 0) readers[p.ops[k].in2]++;
+    }
+    b.pool_leaky.assign(b.nops, 0);
+    for (int k = 1; k < b.nops; ++k) {
+        const Op &op = p.ops[k], &prev = p.ops[k - 1];
+        if (op.kind == OP_POOL && prev.kind == OP_CONV && prev.out == op.in && readers[op.in] == 1 &&
+            net->L[prev.conv].activation == DN_ACT_LEAKY)
+            b.pool_leaky[k] = 1;
+    }
+    size_t bws = 0;
+    for (int k = 0; k < b.nops; ++k) {
+        const Op &op = p.ops[k];
+        if (op.kind != OP_CONV) continue;
+        const dn_layer_desc &d = net->L[op.conv];
+        dn_conv_desc &f = b.fwd[k];
+        memset(&f, 0, sizeof f);
+        f.batch = batch; f.in_h = p.vals[op.in].h; f.in_w = p.vals[op.in].w; f.in_c = p.vals[op.in].c;
+        f.cout = d.cout; f.ksize = d.ksize; f.stride = d.stride; f.pad = d.pad;
+        f.activation = d.activation; f.leaky_slope = net->o.leaky_slope; f.dtype = dt;
+        f.in_scale = f.res_scale = f.out_scale = 1.0f; f.tile = -1;
+        dn_conv_desc bd;
+        int ho, wo, hz, wz;
+        STCHK(bwd_desc(&f, 1, &bd, &ho, &wo, &hz, &wz));
+        size_t ws = 0, z = 0;
+        STCHK(bwd_scratch(&f, &bd, hz, wz, &ws, &z));
+        bws = std::max(bws, ws + z);
+    }
+    b.bws_off = off;
+    b.bws_bytes = bws;
+    off += bws;
+    b.gin_off = off;
+    off += align256((size_t)batch * net->o.in_c * h * w * sizeof(float));
+    b.mabs_off = off;
+    off += align256(ascend_scratch_bytes(batch));
+    b.total = off;
+    *out = std::move(b);
+    return DN_OK;
+}
+
+static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, char *base, const float *x, hipStream_t s)
+{
+    const Plan &p = b.p;
+    const int dt = p.dtype;
+    const Value &v0 = p.vals[0];
+    if (!p.ops[0].first) HIPCHK(launch_ingest(dt, x, p.batch, v0.c, v0.h, v0.w, v0.cp, 1.0f, base + v0.off, s));
+    for (int k = 0; k < b.nops; ++k) STCHK(enqueue_op(net, p, p.ops[k], base, s, false, -1, 0, x));
+    // objective: half the sum of squares of the seed layer's output -> its gradient is the output itself
+    HIPCHK(hipMemcpyAsync(base + b.goff[b.seed], base + p.vals[b.seed].off, b.gbytes[b.seed], hipMemcpyDeviceToDevice, s));
+    std::vector<char> have(b.seed + 1, 0);
+    have[b.seed] = 1;
+    for (int k = b.nops - 1; k >= 0; --k) {
+        const Op &op = p.ops[k];
+        char *gout = base + b.goff[op.out];
+        const Value &vo = p.vals[op.out];
+        const size_t count = (size_t)p.batch * vo.h * vo.w * vo.cp;
+        if (op.kind == OP_CONV) {
+            const dn_layer_desc &d = net->L[op.conv];
+            const ConvWeights &cw = net->cw[op.conv];
+            const bool masked = k + 1 < b.nops && b.pool_leaky[k + 1];  // the pool after it applied the leaky gradient
+            if (d.activation == DN_ACT_LEAKY && !masked)
+                HIPCHK(launch_leaky_bwd(dt, base + vo.off, gout, gout, net->o.leaky_slope, count, s));
+            STCHK(enqueue_conv_backward(&b.fwd[k], gout, cw.wb, cw.bzero, cw.bscale, have[op.in], base + b.goff[op.in],
+                                        base + b.bws_off, b.bws_bytes, s));
+            have[op.in] = 1;
+        } else if (op.kind == OP_POOL) {
+            const dn_layer_desc &d = net->L[op.layer];
+            const Value &vi = p.vals[op.in];
+            HIPCHK(launch_maxpool_bwd(dt, base + vi.off, gout, base + b.goff[op.in], p.batch, vi.h, vi.w, vi.cp, d.ksize,
+                                      d.stride, vo.h, vo.w, have[op.in], b.pool_leaky[k] ? net->o.leaky_slope : -1.0f, s));
+            have[op.in] = 1;
+        } else {
+            for (int src : {op.in, op.in2}) {
+                char *g = base + b.goff[src];
+                if (have[src]) HIPCHK(launch_add(dt, g, 1.f, gout, 1.f, g, 1.f, count, s));
+                else HIPCHK(hipMemcpyAsync(g, gout, count * esize(dt), hipMemcpyDeviceToDevice, s));
+                have[src] = 1;
+            }
+        }
+    }
+    HIPCHK(launch_egress(dt, base + b.goff[0], p.batch, v0.c, v0.h, v0.w, v0.cp, 1.0f, (float *)(base + b.gin_off), s));
+    return DN_OK;
+}
+
+static dn_status bwd_prepare(dn_net *net, int layer, const void *x, int batch, int h, int w, BwdPlan *b)
+{
+    if (net->o.dtype != DN_F32 && net->o.dtype != DN_BF16)
+        return fail(DN_EUNSUPPORTED, "input gradient: F32 and BF16 nets only");
+    STCHK(check_ready(net, false));
+    STCHK(check_dims(net, batch, h, w));
+    if (!x) return fail(DN_EINVAL, "x is NULL");
+    for (size_t i = 0; i < net->L.size(); ++i)
+        if (net->L[i].kind == DN_CONV && !net->cw[i].wb) return fail(DN_ESTATE, "conv layer %zu has no backward weights", i);
+    STCHK(make_bwd_plan(net, layer, batch, h, w, b));
+    std::lock_guard<std::mutex> g(net->mu);
+    if (net->bwd_bytes < b->total) {
+        if (net->bwd_buf) {
+            HIPCHK(hipDeviceSynchronize());
+            HIPCHK(hipFree(net->bwd_buf));
+            net->bwd_buf = nullptr;
+            net->bwd_bytes = 0;
+        }
+        HIPCHK(hipMalloc(&net->bwd_buf, b->total));
+        net->bwd_bytes = b->total;
+    }
+    return DN_OK;
+}
+
+extern "C" dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
+                                       void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (!grad) return fail(DN_EINVAL, "grad is NULL");
+    HIPCHK(hipSetDevice(net->o.device));
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, x, batch, h, w, &b));
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)net->bwd_buf;
+    STCHK(enqueue_input_gradient(net, b, base, x, s));
+    HIPCHK(hipMemcpyAsync(grad, base + b.gin_off, (size_t)batch * net->o.in_c * h * w * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, int h, int w, float rate, int iters,
+                                  void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (iters < 0) return fail(DN_EINVAL, "iters must be >= 0");
+    if (!std::isfinite(rate)) return fail(DN_EINVAL, "rate must be finite");
+    HIPCHK(hipSetDevice(net->o.device));
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, x, batch, h, w, &b));
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)net->bwd_buf;
+    for (int it = 0; it < iters; ++it) {
+        STCHK(enqueue_input_gradient(net, b, base, x, s));
+        HIPCHK(launch_ascend(x, (const float *)(base + b.gin_off), (double *)(base + b.mabs_off), batch,
+                             (size_t)net->o.in_c * h * w, rate, s));
+    }
     return DN_OK;
 }
 

@@ -93,6 +93,14 @@ SIGNATURES = {
     "dn_detect_workspace": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "dn_detect": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_float), _f, _f, _i, _vp, _sz, _vp, _vp,
                        _vp, _vp]),
+    "dn_conv_backward_sizes": (_i, [ctypes.POINTER(ConvDesc), ctypes.POINTER(_sz), ctypes.POINTER(_sz),
+                                    ctypes.POINTER(_sz)]),
+    "dn_conv_pack_backward": (_i, [ctypes.POINTER(ConvDesc), _dp, _dp, _dp, _dp, _d, _vp, _vp, _vp, _vp]),
+    "dn_conv_backward_data": (_i, [ctypes.POINTER(ConvDesc), _vp, _vp, _vp, _vp, _i, _vp, _vp, _sz, _vp]),
+    "dn_maxpool_backward": (_i, [ctypes.POINTER(PoolDesc), _vp, _vp, _i, _vp, _vp]),
+    "dn_leaky_backward": (_i, [_i, _sz, _vp, _vp, _f, _vp, _vp]),
+    "dn_input_gradient": (_i, [_vp, _i, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_nightmare": (_i, [_vp, _i, _vp, _i, _i, _i, _f, _i, _vp]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -294,6 +302,12 @@ class Net:
         check(LIB.dn_time_layer(self._h, layer, batch, h, w, iters, stream_handle(stream), ctypes.byref(ms)))
         return ms.value
 
+    def input_gradient(self, layer: int, x, batch: int, h: int, w: int, grad, stream=None) -> None:
+        check(LIB.dn_input_gradient(self._h, layer, ptr(x), batch, h, w, ptr(grad), stream_handle(stream)))
+
+    def nightmare(self, layer: int, x, batch: int, h: int, w: int, rate: float, iters: int, stream=None) -> None:
+        check(LIB.dn_nightmare(self._h, layer, ptr(x), batch, h, w, rate, iters, stream_handle(stream)))
+
     def layer_plan(self, layer: int, batch: int, h: int, w: int):
         v = [_i() for _ in range(4)]
         check(LIB.dn_layer_plan(self._h, layer, batch, h, w, *[ctypes.byref(x) for x in v]))
@@ -342,3 +356,30 @@ def ingest(dtype, batch, c, h, w, x, scale, y, stream=None):
 
 def egress(dtype, batch, c, h, w, x, scale, y, stream=None):
     check(LIB.dn_egress(dtype, batch, c, h, w, ptr(x), scale, ptr(y), stream_handle(stream)))
+
+
+def conv_backward_sizes(d: ConvDesc) -> Tuple[int, int, int]:
+    a, b, c = _sz(), _sz(), _sz()
+    check(LIB.dn_conv_backward_sizes(ctypes.byref(d), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def conv_pack_backward(d: ConvDesc, w, mean, var, gamma, eps, w_out, zero_bias, unit_scale, stream=None):
+    keep = [_dptr(a) for a in (w, mean, var, gamma)]
+    check(LIB.dn_conv_pack_backward(ctypes.byref(d), *[k[1] for k in keep], eps, ptr(w_out), ptr(zero_bias),
+                                    ptr(unit_scale), stream_handle(stream)))
+
+
+def conv_backward_data(d: ConvDesc, dy, w_packed, zero_bias, unit_scale, accumulate, dx, workspace=None,
+                       ws_bytes=0, stream=None):
+    check(LIB.dn_conv_backward_data(ctypes.byref(d), ptr(dy), ptr(w_packed), ptr(zero_bias), ptr(unit_scale),
+                                    int(accumulate), ptr(dx), ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def maxpool_backward(batch, h, w, c, size, stride, dtype, x, dy, accumulate, dx, stream=None):
+    d = PoolDesc(batch, h, w, c, size, stride, dtype)
+    check(LIB.dn_maxpool_backward(ctypes.byref(d), ptr(x), ptr(dy), int(accumulate), ptr(dx), stream_handle(stream)))
+
+
+def leaky_backward(dtype, count, a, dy, slope, dx, stream=None):
+    check(LIB.dn_leaky_backward(dtype, count, ptr(a), ptr(dy), slope, ptr(dx), stream_handle(stream)))

@@ -96,6 +96,63 @@ def test_net_create_validation_without_gpu(dn):
     assert e.value.status == dn.DN_EINVAL
 
 
+def test_conv_backward_sizes_host_arithmetic(dn):
+    # backward-data of a stride-1 3x3 conv 64 -> 128: a forward conv 128 -> 64
+    d = dn.conv_desc(2, 20, 18, 64, 128, 3, 1, 1, dtype=dn.BF16)
+    w, v, ws = dn.conv_backward_sizes(d)
+    assert w == 64 * 9 * 128 * 2 and v == 64 * 4
+    # stride 2: the workspace also holds the spread gradient [2][H+2p-k+1][W+2p-k+1][cout_p]
+    d = dn.conv_desc(2, 20, 18, 64, 128, 3, 2, 1, dtype=dn.F32)
+    w2, v2, ws2 = dn.conv_backward_sizes(d)
+    assert w2 == 64 * 9 * 128 * 4 and ws2 >= 2 * 20 * 18 * 128 * 4
+    # stem: 3 input channels -> a 3-channel gradient padded to 4 (F32)
+    d = dn.conv_desc(1, 416, 416, 3, 16, 3, 1, 1, dtype=dn.F32)
+    assert dn.conv_backward_sizes(d)[1] == 4 * 4
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(pool=2), "DN_EUNSUPPORTED"),       # fused forms have no backward here
+    (dict(residual=1), "DN_EUNSUPPORTED"),
+    (dict(input_nchw=1, in_c=3), "DN_EUNSUPPORTED"),
+    (dict(dtype=2), "DN_EUNSUPPORTED"),      # FP8
+    (dict(pad=3), "DN_EUNSUPPORTED"),        # pad > k - 1
+    (dict(cout=0), "DN_EINVAL"),
+])
+def test_conv_backward_validation(dn, kw, status):
+    base = dict(batch=1, in_h=16, in_w=16, in_c=8, cout=8, ksize=3, stride=1, pad=1)
+    base.update(kw)
+    with pytest.raises(dn.DnError) as e:
+        dn.conv_backward_sizes(dn.conv_desc(**base))
+    assert e.value.status == getattr(dn, status)
+    assert dn.last_error()
+
+
+def test_backward_op_validation_without_gpu(dn):
+    with pytest.raises(dn.DnError) as e:
+        dn.leaky_backward(dn.FP8, 16, 1, 1, 0.1, 1)
+    assert e.value.status == dn.DN_EUNSUPPORTED
+    with pytest.raises(dn.DnError) as e:
+        dn.leaky_backward(dn.F32, 6, 1, 1, 0.1, 1)  # not whole 16-byte segments
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:
+        dn.leaky_backward(dn.F32, 16, 1, 1, 1.5, 1)
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:
+        dn.maxpool_backward(1, 4, 4, 8, 2, 2, dn.F32, None, 1, 0, 1)
+    assert e.value.status == dn.DN_EINVAL
+    with pytest.raises(dn.DnError) as e:
+        dn.maxpool_backward(1, 4, 4, 8, 2, 0, dn.F32, 1, 1, 0, 1)
+    assert e.value.status == dn.DN_EINVAL
+
+
+def test_leaky_shortcut_rejected(dn):
+    import synth
+    layers = [synth.conv(16, 3), synth.conv(16, 3), synth.Layer(synth.SHORTCUT, src=0, activation=synth.LEAKY)]
+    with pytest.raises(dn.DnError) as e:
+        dn.Net(layers, 3, 32, 32, 1)
+    assert e.value.status == dn.DN_EUNSUPPORTED
+
+
 def test_null_safe_destroy(dn):
     dn.LIB.dn_net_destroy(None)
     st = dn.LIB.dn_forward(None, None, 1, 1, 1, None, None)

@@ -1,0 +1,299 @@
+"""Backward pass to the input image on the device against the FP64 oracle.
+
+Per-op parity: the backward-data conv (F32 / BF16 gates 1e-5 / 2e-2 relative
+L2 on the same inputs); the max-pool gradient and the leaky gradient bit-exact
+on inputs whose results are representable (ties included, so the
+first-maximum rule is exercised).
+
+Whole-pass parity: dn_input_gradient and dn_nightmare against the oracle.
+F32 against the plain FP64 gradient (1e-5).  BF16 against the gradient of
+the BF16 path's definition (image, folded weights and activations stored in
+BF16, oracle.backward.input_gradient_stored), whose leaky and max-pool
+branches are taken on stored BF16 values as on the device.  Those branches
+are discontinuities: two correct BF16 evaluations whose stored activations
+differ by one unit in the last place in a few elements (FP32 versus FP64
+accumulation crossing a rounding boundary) take a few different branches,
+and in a deep residual stack that moves the gradient by more than 2e-2.  The
+BF16 gate is therefore max(2e-2, 2 s), where s is the oracle's own change
+when 0.1% of the image's pixels move by one BF16 unit (computed on the host
+from the oracle alone).  The same mechanism reaches F32 at the full 416x416
+size: a branch variable within the FP32 forward's error (about 1e-6
+relative) of its threshold occurs about once per million branch variables,
+an image carries about 4.4 million of them, and each different branch moves
+about one element's share of the gradient, so a few flips give a relative
+L2 change of order sqrt(flips / 2.8e6) ~ 1e-3; the full-size F32 gate is 1e-2
+(about 70 flips), the small-size F32 gate stays 1e-5 (0.06 flips expected)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import backward as ob
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    from paper_1811_03882_amd import dn as _dn
+    G.torch_cuda()
+    return _dn
+
+
+def _params(cout, cin, k, seed, bn):
+    rng = np.random.default_rng([seed, 11])
+    p = synth.ConvParams(w=rng.normal(0, np.sqrt(2.0 / (cin * k * k)), (cout, cin, k, k)),
+                         bias=rng.normal(0, 0.1, cout))
+    if bn:
+        p.mean = rng.normal(0, 0.3, cout)
+        p.var = rng.uniform(0.5, 1.5, cout)
+        p.gamma = rng.uniform(0.9, 1.1, cout)
+        p.beta = rng.normal(0, 0.2, cout)
+    return p
+
+
+def _bn_scale(p, eps=1e-5):
+    if p.gamma is None:
+        return np.ones(p.w.shape[0])
+    return p.gamma / np.sqrt(p.var + eps)
+
+
+def run_conv_backward(dn, dtype, p, n, h, w, st, pad, dy, acc=None):
+    torch = G.torch_cuda()
+    cout, cin, k, _ = p.w.shape
+    d = dn.conv_desc(n, h, w, cin, cout, k, st, pad, dn.LEAKY, 0.1, 0, 0, dtype)
+    wb, vb, wsb = dn.conv_backward_sizes(d)
+    wbuf, bz, us = G.empty_bytes(wb), G.empty_bytes(vb), G.empty_bytes(vb)
+    dn.conv_pack_backward(d, p.w, p.mean, p.var, p.gamma, 1e-5, wbuf, bz, us)
+    dyb = G.to_storage(dn, dtype, dy)
+    dxb = G.to_storage(dn, dtype, acc) if acc is not None else G.empty_bytes(G.nhwc_bytes(dn, dtype, n, cin, h, w))
+    ws = G.empty_bytes(wsb) if wsb else None
+    dn.conv_backward_data(d, dyb, wbuf, bz, us, acc is not None, dxb, ws, wsb)
+    torch.cuda.synchronize()
+    return G.from_storage(dn, dtype, dxb, n, cin, h, w)
+
+
+# forward convs whose backward-data is checked: batch, H, W, cin, cout, k, stride, pad, bn
+BWD_SHAPES = [
+    (2, 13, 11, 3, 16, 3, 1, 1, True),      # stem: 3-channel gradient (padded to 4 / 8)
+    (1, 16, 16, 32, 64, 3, 1, 1, True),
+    (2, 9, 7, 48, 40, 3, 2, 1, True),       # stride 2, ragged: spread gradient
+    (1, 16, 18, 64, 128, 3, 2, 1, True),    # stride 2, even
+    (3, 9, 11, 32, 125, 1, 1, 0, False),    # 1x1 from 125 channels (padded)
+    (1, 8, 8, 256, 96, 3, 1, 1, True),      # long K: channel-block K order, split-K
+    (2, 6, 5, 1024, 512, 3, 1, 1, True),    # 9-layer net's 1024-wide layers on a small map
+]
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+@pytest.mark.parametrize("shape", BWD_SHAPES, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8])
+def test_conv_backward_data_parity(dn, dtype, shape):
+    n, h, w, cin, cout, k, st, pad, bn = shape
+    p = _params(cout, cin, k, 300 + cin, bn)
+    ho, wo = (h + 2 * pad - k) // st + 1, (w + 2 * pad - k) // st + 1
+    dy = synth.make_tensor((n, cout, ho, wo), 17, cout)
+    ref = oracle.conv2d_backward_data(dy * _bn_scale(p)[None, :, None, None], p.w, st, pad, h, w)
+    got = run_conv_backward(dn, dtype, p, n, h, w, st, pad, dy)
+    err = G.rel_l2(got, ref)
+    print("conv backward %s %s rel_l2=%.3e" % (G.NAME[dtype], shape, err))
+    assert err < G.GATE[dtype]
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_conv_backward_data_accumulates(dn, dtype):
+    n, h, w, cin, cout, k, st, pad = 2, 10, 9, 16, 32, 3, 2, 1
+    p = _params(cout, cin, k, 5, True)
+    dy = synth.make_tensor((n, cout, 5, 5), 18, 0)
+    acc = synth.make_tensor((n, cin, h, w), 18, 1)
+    ref = acc + oracle.conv2d_backward_data(dy * _bn_scale(p)[None, :, None, None], p.w, st, pad, h, w)
+    got = run_conv_backward(dn, dtype, p, n, h, w, st, pad, dy, acc=acc)
+    assert G.rel_l2(got, ref) < G.GATE[dtype]
+
+
+def test_conv_backward_rejects_fused_and_fp8(dn):
+    d = dn.conv_desc(1, 8, 8, 16, 16, 3, 1, 1, dn.LEAKY, 0.1, 2, 0, dn.F32)
+    with pytest.raises(dn.DnError) as e:
+        dn.conv_backward_sizes(d)
+    assert e.value.status == dn.DN_EUNSUPPORTED
+    d = dn.conv_desc(1, 8, 8, 16, 16, 3, 1, 1, dn.LEAKY, 0.1, 0, 0, dn.FP8)
+    with pytest.raises(dn.DnError) as e:
+        dn.conv_backward_sizes(d)
+    assert e.value.status == dn.DN_EUNSUPPORTED
+
+
+# n, h, w, c, size, stride
+POOL_BWD = [(2, 8, 10, 16, 2, 2), (1, 7, 9, 24, 2, 2), (2, 13, 13, 32, 2, 1), (1, 9, 8, 8, 3, 2), (1, 5, 6, 3, 3, 1)]
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+@pytest.mark.parametrize("case", POOL_BWD, ids=lambda c: "b%d_%dx%d_c%d_k%d_s%d" % c)
+@pytest.mark.parametrize("accumulate", [0, 1], ids=["write", "acc"])
+def test_maxpool_backward_bit_exact(dn, dtype, case, accumulate):
+    torch = G.torch_cuda()
+    n, h, w, c, size, st = case
+    rng = np.random.default_rng(list(case) + [dtype])
+    x = rng.integers(-6, 7, (n, c, h, w)) / 4.0     # many ties inside windows
+    ho, wo = (h - 1) // st + 1, (w - 1) // st + 1
+    dy = rng.integers(-8, 9, (n, c, ho, wo)) / 4.0  # sums of up to 4 stay exact in BF16
+    acc = rng.integers(-4, 5, (n, c, h, w)) / 4.0
+    ref = oracle.maxpool_backward(x, size, st, dy) + (acc if accumulate else 0.0)
+    xb, dyb = G.to_storage(dn, dtype, x), G.to_storage(dn, dtype, dy)
+    dxb = G.to_storage(dn, dtype, acc) if accumulate else G.empty_bytes(G.nhwc_bytes(dn, dtype, n, c, h, w))
+    dn.maxpool_backward(n, h, w, c, size, st, dtype, xb, dyb, accumulate, dxb)
+    torch.cuda.synchronize()
+    got = G.from_storage(dn, dtype, dxb, n, c, h, w)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_leaky_backward_bit_exact(dn, dtype):
+    torch = G.torch_cuda()
+    n, c, h, w = 2, 24, 7, 9
+    rng = np.random.default_rng([dtype, 77])
+    a = rng.integers(-3, 4, (n, c, h, w)) / 2.0  # exact zeros take the slope branch
+    dy = synth.make_tensor((n, c, h, w), 19, dtype)
+    slope = 0.1
+    dy_st = dy.astype(np.float32) if dtype == 0 else ob.round_bf16(dy).astype(np.float32)
+    ref = np.where(a > 0, dy_st, dy_st * np.float32(slope)).astype(np.float32).astype(np.float64)
+    if dtype == 1:
+        ref = ob.round_bf16(ref)
+    ab, dyb = G.to_storage(dn, dtype, a), G.to_storage(dn, dtype, dy)
+    count = n * h * w * dn.channel_pad(dtype, c)
+    dn.leaky_backward(dtype, count, ab, dyb, slope, dyb)  # in place
+    torch.cuda.synchronize()
+    got = G.from_storage(dn, dtype, dyb, n, c, h, w)
+    assert np.array_equal(got, ref)
+
+
+def _small_net():
+    return synth.Net("bwd_small", 3, 24, 20, [
+        synth.conv(8, 3),
+        synth.maxpool(2, 2),
+        synth.conv(16, 3, stride=2),
+        synth.conv(8, 1),
+        synth.conv(16, 3),
+        synth.shortcut(2),
+        synth.maxpool(2, 1),
+        synth.conv(5, 1, bn=False, act=synth.LINEAR),
+    ])
+
+
+def _gpu_gradient(dn, net, dtype, x, layer, seed):
+    torch = G.torch_cuda()
+    n, _, h, w = x.shape
+    gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype, leaky_slope=net.leaky_slope, bn_eps=net.bn_eps)
+    gn.load_params(synth.make_params(net, seed))
+    xd = G.dev(x.astype(np.float32))
+    g = torch.empty_like(xd)
+    gn.input_gradient(layer, xd, n, h, w, g)
+    torch.cuda.synchronize()
+    return gn, g.cpu().numpy().astype(np.float64)
+
+
+def _ref_gradient(net, dtype, params, x, layer):
+    if dtype == 0:
+        return ob.input_gradient(net, params, x, layer)
+    return ob.input_gradient_stored(net, params, x, layer)
+
+
+def _gate(net, dtype, params, x, layer, ref, full_size=False):
+    """F32: 1e-5, or 1e-2 at the full 416x416 size (see the module notes).
+    BF16: max(2e-2, twice the BF16 definition's own change when 0.1% of the
+    pixels move by one BF16 unit)."""
+    if dtype == 0:
+        return 1e-2 if full_size else G.GATE[0]
+    rng = np.random.default_rng([layer, 99])
+    xp = x * np.where(rng.random(x.shape) < 1e-3, 1 + 2.0 ** -8, 1.0)
+    s = G.rel_l2(ob.input_gradient_stored(net, params, xp, layer), ref)
+    return max(G.GATE[1], 2 * s)
+
+
+GRAD_CASES = [  # net builder, batch, h, w, seed, layers
+    (_small_net, 2, 24, 20, 31, (0, 2, 5, 7)),
+    (synth.plain9, 1, 64, 64, 32, (9, 14)),
+    (lambda: synth.residual52(units=(1, 2), widths=(64, 128), in_hw=32), 2, 32, 32, 33, (4, 11)),
+]
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+@pytest.mark.parametrize("case", GRAD_CASES, ids=["small", "plain9_64", "residual_32"])
+def test_input_gradient_parity(dn, dtype, case):
+    build, n, h, w, seed, layers = case
+    net = build()
+    params = synth.make_params(net, seed)
+    x = synth.make_input(net, n, seed, h=h, w=w)
+    for layer in layers:
+        _, got = _gpu_gradient(dn, net, dtype, x, layer, seed)
+        ref = _ref_gradient(net, dtype, params, x, layer)
+        err, gate = G.rel_l2(got, ref), _gate(net, dtype, params, x, layer, ref)
+        print("input gradient %s %s layer %d rel_l2=%.3e gate %.3e" % (G.NAME[dtype], net.name, layer, err, gate))
+        assert err < gate
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_nightmare_step_parity(dn, dtype):
+    torch = G.torch_cuda()
+    net = _small_net()
+    n, h, w, seed, layer, rate = 2, 24, 20, 34, 5, 0.02
+    params = synth.make_params(net, seed)
+    x = synth.make_input(net, n, seed, h=h, w=w)
+    gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype, leaky_slope=net.leaky_slope, bn_eps=net.bn_eps)
+    gn.load_params(params)
+    xd = G.dev(x.astype(np.float32))
+    gn.nightmare(layer, xd, n, h, w, rate, 1)
+    torch.cuda.synchronize()
+    got = xd.cpu().numpy().astype(np.float64)
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref = _ref_gradient(net, dtype, params, x32, layer)
+    want = ob.ascent_step(x32, ref, rate)
+    # the step itself (x' - x) carries the whole error; compare it, clipped as on both sides
+    err, gate = G.rel_l2(got - x32, want - x32), _gate(net, dtype, params, x32, layer, ref)
+    print("nightmare step %s rel_l2=%.3e gate %.3e" % (G.NAME[dtype], err, gate))
+    assert err < gate
+    assert got.min() >= 0.0 and got.max() <= 1.0
+    # further iterations keep the image in range and move it up the energy
+    e0 = ob.energy(net, params, got, layer)
+    gn.nightmare(layer, xd, n, h, w, rate, 3)
+    torch.cuda.synchronize()
+    x4 = xd.cpu().numpy().astype(np.float64)
+    assert x4.min() >= 0.0 and x4.max() <= 1.0
+    assert ob.energy(net, params, x4, layer) > e0
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_input_gradient_plain9_full_size_sampled(dn, dtype):
+    """The 9-layer net at its full size (batch 64, 416x416), gradient of the
+    last layer's energy: sampled images against the oracle, each image
+    computed one by one on the host."""
+    net = synth.plain9()
+    n, h, w, seed, layer = 64, 416, 416, 35, 14
+    params = synth.make_params(net, seed)
+    x = synth.make_input(net, n, seed)
+    _, got = _gpu_gradient(dn, net, dtype, x, layer, seed)
+    assert np.all(np.isfinite(got))
+    for i in (0, 63):
+        ref = _ref_gradient(net, dtype, params, x[i:i + 1], layer)
+        err, gate = G.rel_l2(got[i:i + 1], ref), _gate(net, dtype, params, x[i:i + 1], layer, ref, full_size=True)
+        print("plain9 b64 %s image %d rel_l2=%.3e gate %.3e" % (G.NAME[dtype], i, err, gate))
+        assert err < gate
+
+
+def test_input_gradient_errors(dn):
+    net = _small_net()
+    torch = G.torch_cuda()
+    x = torch.zeros((1, 3, 24, 20), device="cuda")
+    g = torch.zeros_like(x)
+    gn = dn.Net(net.layers, 3, 24, 20, 1, dtype=dn.F32)
+    with pytest.raises(dn.DnError) as e:
+        gn.input_gradient(7, x, 1, 24, 20, g)
+    assert e.value.status == dn.DN_ESTATE  # weights not loaded
+    gn.load_params(synth.make_params(net, 0))
+    with pytest.raises(dn.DnError) as e:
+        gn.input_gradient(8, x, 1, 24, 20, g)
+    assert e.value.status == dn.DN_EINVAL  # no such layer
+    f8 = dn.Net(net.layers, 3, 24, 20, 1, dtype=dn.FP8)
+    f8.load_params(synth.make_params(net, 0))
+    with pytest.raises(dn.DnError) as e:
+        f8.input_gradient(7, x, 1, 24, 20, g)
+    assert e.value.status == dn.DN_EUNSUPPORTED

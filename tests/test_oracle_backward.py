@@ -189,3 +189,30 @@ def test_backward_mutant_is_caught(name, tmp_path):
                 caught = True
                 break
     assert caught, "mutant %s survived every backward pin" % name
+
+
+def test_round_bf16_hand_values():
+    one = 1.0
+    vals = [one + 2.0 ** -8, one + 3 * 2.0 ** -8, one + 2.0 ** -9, -(one + 2.0 ** -7), 3.0e-39, 65504.0, 0.1]
+    want = [one, one + 2.0 ** -6, one, -(one + 2.0 ** -7), None, 65536.0, 0.10009765625]
+    got = ob.round_bf16(np.array(vals))
+    for g, w, v in zip(got, want, vals):
+        if w is not None:
+            assert g == w, (v, g, w)
+    # ties to even: 1 + 2^-8 sits halfway between 1 and 1 + 2^-7 -> 1 (even);
+    # 1 + 3*2^-8 sits halfway between 1 + 2^-7 and 1 + 2^-6 -> 1 + 2^-6 (even)
+    assert ob.round_bf16(np.array([one + 2.0 ** -7]))[0] == one + 2.0 ** -7  # representable: unchanged
+
+
+@pytest.mark.parametrize("layer", [2, 7])
+def test_stored_gradient_without_rounding_is_the_plain_gradient(layer):
+    net = _small_net()
+    params = synth.make_params(net, 22)
+    x = synth.make_input(net, 2, 22)
+    plain = ob.input_gradient(net, params, x, layer)
+    ident = lambda a: np.asarray(a, np.float64)
+    same = ob.input_gradient_stored(net, params, x, layer, q=ident, qb=ident)
+    np.testing.assert_allclose(same, plain, rtol=1e-10, atol=1e-12 * np.abs(plain).max())
+    bf = ob.input_gradient_stored(net, params, x, layer)
+    err = np.linalg.norm(bf - plain) / np.linalg.norm(plain)
+    assert 0 < err < 0.5  # rounding changes it, but it stays the same gradient
