@@ -64,52 +64,42 @@ __global__ void __launch_bounds__(256) maxpool_bwd_tiled(const void *x, const vo
     const size_t q = p / wo;
     const int oi = (int)(q % ho);
     const int img = (int)(q / ho);
-    const int off = (size - 1) / 2;
     const uint4 *X = (const uint4 *)x;
-    float m[E];
+    // the window (size <= 2, no offset) stays in registers: x is read once
+    float f[4][E], m[E];
+    size_t o[4];
+    bool in[4];
     int at[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) { m[e] = -INFINITY; at[e] = -1; }
-    for (int u = 0; u < size; ++u) {
-        const int yy = oi * size - off + u;
-        if (yy < 0 || yy >= h) continue;
-        for (int v = 0; v < size; ++v) {
-            const int xx = oj * size - off + v;
-            if (xx < 0 || xx >= w) continue;
-            float f[E];
-            Seg<DT>::dec(X[(((size_t)img * h + yy) * w + xx) * nseg + sg], f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int u = k >> 1, v = k & 1;
+        const int yy = oi * size + u, xx = oj * size + v;
+        in[k] = u < size && v < size && yy < h && xx < w;
+        o[k] = (((size_t)img * h + yy) * w + xx) * nseg + sg;
+        if (in[k]) {
+            Seg<DT>::dec(X[o[k]], f[k]);
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                if (f[e] > m[e]) { m[e] = f[e]; at[e] = u * size + v; }
+                if (f[k][e] > m[e]) { m[e] = f[k][e]; at[e] = k; }
         }
     }
     float d[E];
     Seg<DT>::dec(((const uint4 *)dy)[t], d);
-    for (int u = 0; u < size; ++u) {
-        const int yy = oi * size - off + u;
-        if (yy < 0 || yy >= h) continue;
-        for (int v = 0; v < size; ++v) {
-            const int xx = oj * size - off + v;
-            if (xx < 0 || xx >= w) continue;
-            const size_t o = (((size_t)img * h + yy) * w + xx) * nseg + sg;
-            float g[E];
-            if (mask >= 0.0f) {
-                float f[E];
-                Seg<DT>::dec(X[o], f);
 #pragma unroll
-                for (int e = 0; e < E; ++e) g[e] = at[e] == u * size + v ? d[e] * leaky_factor(f[e], mask) : 0.0f;
-            } else {
+    for (int k = 0; k < 4; ++k) {
+        if (!in[k]) continue;
+        float g[E];
 #pragma unroll
-                for (int e = 0; e < E; ++e) g[e] = at[e] == u * size + v ? d[e] : 0.0f;
-            }
-            if (accumulate) {
-                float o2[E];
-                Seg<DT>::dec(((const uint4 *)dx)[o], o2);
+        for (int e = 0; e < E; ++e) g[e] = at[e] == k ? d[e] * leaky_factor(f[k][e], mask) : 0.0f;
+        if (accumulate) {
+            float o2[E];
+            Seg<DT>::dec(((const uint4 *)dx)[o[k]], o2);
 #pragma unroll
-                for (int e = 0; e < E; ++e) g[e] = o2[e] + g[e];
-            }
-            ((uint4 *)dx)[o] = Seg<DT>::enc(g);
+            for (int e = 0; e < E; ++e) g[e] = o2[e] + g[e];
         }
+        ((uint4 *)dx)[o[k]] = Seg<DT>::enc(g);
     }
 }
 
