@@ -485,6 +485,39 @@ def main():
         log("[bench] jacobi: resident %.4f ms/iter, per-iteration transfer %.3f ms/iter" % (ms_res, ms_pl))
         del uj, wj, uh
 
+        # Deep residual CNN (52 convs, 23 shortcuts), BF16, batch 16, 3x256x256
+        log("[bench] residual52 bf16 b16")
+        rnet = synth.residual52()
+        rparams = synth.make_params(rnet, synth.SEED_RESIDUAL)
+        RB, RH = 16, 256
+        xr = torch.from_numpy(synth.make_input(rnet, RB, synth.SEED_RESIDUAL).astype(np.float32)).cuda()
+        n6, a6 = build_net(dn, torch, rnet, dn.BF16, RB, RH, RH, params=rparams)
+        yr6 = torch.empty((RB,) + n6.output_shape(RH, RH), device="cuda")
+        w6, p6 = time_steps(torch, lambda: n6.forward(xr, RB, RH, RH, yr6, stream), 200, 10, stream)
+        rfl = sum(v[0] for v in conv_flops(rnet, RB, RH, RH).values())
+        ms6 = float(np.mean(p6))
+        secondary.append({"workload": "52-layer residual CNN bf16 b16 3x256x256 graph (stem, 5 stride-2 stages, 23 units)",
+                          "images_per_s": RB * len(p6) / w6, "ms_per_step": w6 * 1e3 / len(p6),
+                          "p50_ms": float(np.percentile(p6, 50)), "p99_ms": float(np.percentile(p6, 99)),
+                          "gflop_per_batch": rfl / 1e9, "conv_tflops": rfl / (ms6 * 1e-3) / 1e12,
+                          "conv_pct_peak": 100.0 * rfl / (ms6 * 1e-3) / PEAK["bf16"]})
+        log("[bench] residual52: %.3f ms per batch of 16" % ms6)
+        n6.close()
+        del a6, xr, yr6
+
+        # Single conv block, FP32, 1x3x32x32 (launch-bound: latency only)
+        snet = synth.single_block()
+        sparams = synth.make_params(snet, synth.SEED_SINGLE)
+        xs = torch.from_numpy(synth.make_input(snet, 1, synth.SEED_SINGLE).astype(np.float32)).cuda()
+        n7, a7 = build_net(dn, torch, snet, dn.F32, 1, 32, 32, params=sparams)
+        ys = torch.empty((1,) + n7.output_shape(32, 32), device="cuda")
+        _, p7 = time_steps(torch, lambda: n7.forward(xs, 1, 32, 32, ys, stream), 1000, 20, stream)
+        secondary.append({"workload": "single conv block f32 1x3x32x32 graph (conv3x3 16 + BN + leaky + pool)",
+                          "p50_ms": float(np.percentile(p7, 50)), "p99_ms": float(np.percentile(p7, 99)),
+                          "replays": len(p7)})
+        n7.close()
+        del a7, xs, ys
+
         # Image modification (the workload's second program): one gradient-ascent
         # step on the energy of the last layer = unfused forward keeping every
         # layer output + backward to the image + update, batch 64 at 416x416
