@@ -209,15 +209,28 @@ def _gate(net, dtype, params, x, layer, ref, full_size=False):
     return max(G.GATE[1], 2 * s)
 
 
+def _ingest_net():
+    # a 5x5 stem cannot take the first-layer kernel: the image goes through the
+    # ingest kernel, and the stem's backward-data conv has pad 4 - 2 = 2
+    return synth.Net("bwd_ingest", 3, 18, 22, [
+        synth.Layer(synth.CONV, cout=8, ksize=5, stride=1, pad=2, batchnorm=True, activation=synth.LEAKY),
+        synth.maxpool(2, 2),
+        synth.conv(12, 3),
+        synth.maxpool(3, 1),
+        synth.conv(6, 1, bn=False, act=synth.LINEAR),
+    ])
+
+
 GRAD_CASES = [  # net builder, batch, h, w, seed, layers
     (_small_net, 2, 24, 20, 31, (0, 2, 5, 7)),
+    (_ingest_net, 2, 18, 22, 36, (1, 4)),
     (synth.plain9, 1, 64, 64, 32, (9, 14)),
     (lambda: synth.residual52(units=(1, 2), widths=(64, 128), in_hw=32), 2, 32, 32, 33, (4, 11)),
 ]
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
-@pytest.mark.parametrize("case", GRAD_CASES, ids=["small", "plain9_64", "residual_32"])
+@pytest.mark.parametrize("case", GRAD_CASES, ids=["small", "ingest_5x5", "plain9_64", "residual_32"])
 def test_input_gradient_parity(dn, dtype, case):
     build, n, h, w, seed, layers = case
     net = build()
