@@ -57,6 +57,35 @@ template <int DT> __device__ __forceinline__ void store_el(void *p, size_t i, fl
     else if constexpr (DT == BF16) ((uint16_t *)p)[i] = f2bf(v);
     else ((uint8_t *)p)[i] = f2e4m3(v);
 }
+// four consecutive elements (i a multiple of 4), storage type -> FP32, one load
+template <int DT> __device__ __forceinline__ void load4(const void *p, size_t i, float *v)
+{
+    if constexpr (DT == F32) {
+        const float4 t = *reinterpret_cast<const float4 *>((const float *)p + i);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (DT == BF16) {
+        const uint2 t = *reinterpret_cast<const uint2 *>((const uint16_t *)p + i);
+        v[0] = bf2f((uint16_t)(t.x & 0xFFFFu)); v[1] = bf2f((uint16_t)(t.x >> 16));
+        v[2] = bf2f((uint16_t)(t.y & 0xFFFFu)); v[3] = bf2f((uint16_t)(t.y >> 16));
+    } else {
+        const unsigned t = *reinterpret_cast<const unsigned *>((const uint8_t *)p + i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = e4m32f((t >> (8 * j)) & 0xFFu);
+    }
+}
+// four consecutive channels, FP32 values -> storage type, one store
+template <int DT> __device__ __forceinline__ void store4(void *y, size_t idx, const float *v)
+{
+    if constexpr (DT == F32) {
+        *reinterpret_cast<float4 *>((float *)y + idx) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (DT == BF16) {
+        *reinterpret_cast<uint2 *>((uint16_t *)y + idx) =
+            make_uint2((unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16), (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16));
+    } else {
+        *reinterpret_cast<unsigned *>((uint8_t *)y + idx) = (unsigned)f2e4m3(v[0]) | ((unsigned)f2e4m3(v[1]) << 8) |
+                                                            ((unsigned)f2e4m3(v[2]) << 16) | ((unsigned)f2e4m3(v[3]) << 24);
+    }
+}
 
 // ---------------------------------------------------------------- MFMA step
 
@@ -616,31 +645,56 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
 }
 
 // Split-K finish: sum the partials in split order, then the same epilogue.
+// One thread per four consecutive output channels (cout_p is a multiple of 4):
+// 16-byte partial loads, one vector store.
 template <int DT>
 __global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
 {
     const size_t rows = a.pool ? (size_t)(a.M >> 2) : (size_t)a.M;
+    const int cq = a.cout_p >> 2;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * a.cout_p) return;
-    const int col = (int)(idx % a.cout_p);
-    const size_t ro = idx / a.cout_p;
-    const float bias = a.bias[col];
-    const float scl = (DT == FP8) ? a.wscale[col] * a.in_scale : 1.0f;
-    const size_t plane = (size_t)a.M * a.cout_p;
-    auto total = [&](size_t m) {
-        float s = 0.0f;
-        for (int z = 0; z < a.splits; ++z) s += a.partial[z * plane + m * a.cout_p + col];
-        return s;
-    };
-    if (a.pool) {
-        float mx = -INFINITY;
-        for (int q = 0; q < 4; ++q) mx = fmaxf(mx, activate(total(ro * 4 + q) * scl + bias, a.act, a.slope));
-        store_el<DT>(a.y, ro * a.cout_p + col, mx * a.out_inv_scale);
-    } else {
-        float o = activate(total(ro) * scl + bias, a.act, a.slope);
-        if (a.res) o += load_el<DT>(a.res, ro * a.cout_p + col) * a.res_scale;
-        store_el<DT>(a.y, ro * a.cout_p + col, o * a.out_inv_scale);
+    if (idx >= rows * cq) return;
+    const int col = (int)(idx % cq) * 4;
+    const size_t ro = idx / cq;
+    float bias[4], scl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        bias[j] = a.bias[col + j];
+        scl[j] = (DT == FP8) ? a.wscale[col + j] * a.in_scale : 1.0f;
     }
+    const size_t plane = (size_t)a.M * a.cout_p;
+    auto total = [&](size_t m, float *t) {
+        t[0] = t[1] = t[2] = t[3] = 0.0f;
+        for (int z = 0; z < a.splits; ++z) {
+            const float4 p = *reinterpret_cast<const float4 *>(a.partial + z * plane + m * a.cout_p + col);
+            t[0] += p.x; t[1] += p.y; t[2] += p.z; t[3] += p.w;
+        }
+    };
+    float o[4], t[4];
+    if (a.pool) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = -INFINITY;
+        for (int q = 0; q < 4; ++q) {
+            total(ro * 4 + q, t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = fmaxf(o[j], activate(t[j] * scl[j] + bias[j], a.act, a.slope));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
+    } else {
+        total(ro, t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = activate(t[j] * scl[j] + bias[j], a.act, a.slope);
+        if (a.res) {
+            float r[4];
+            load4<DT>(a.res, ro * a.cout_p + col, r);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] += r[j] * a.res_scale;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
+    }
+    store4<DT>(a.y, ro * a.cout_p + col, o);
 }
 
 // Dynamic LDS above the default per-kernel limit must be enabled per kernel.
@@ -696,19 +750,6 @@ template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned cha
     }
 }
 
-// four consecutive channels, FP32 values -> storage type, one store
-template <int DT> __device__ __forceinline__ void store4(void *y, size_t idx, const float *v)
-{
-    if constexpr (DT == F32) {
-        *reinterpret_cast<float4 *>((float *)y + idx) = make_float4(v[0], v[1], v[2], v[3]);
-    } else if constexpr (DT == BF16) {
-        *reinterpret_cast<uint2 *>((uint16_t *)y + idx) =
-            make_uint2((unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16), (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16));
-    } else {
-        *reinterpret_cast<unsigned *>((uint8_t *)y + idx) = (unsigned)f2e4m3(v[0]) | ((unsigned)f2e4m3(v[1]) << 8) |
-                                                            ((unsigned)f2e4m3(v[2]) << 16) | ((unsigned)f2e4m3(v[3]) << 24);
-    }
-}
 
 template <int DT, bool POOL, int CP>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
@@ -1354,8 +1395,9 @@ hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s)
 
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s)
 {
+    if (a.cout_p & 3) return hipErrorInvalidValue;  // channel padding keeps cout_p a multiple of 4
     const size_t rows = a.pool ? (size_t)(a.M >> 2) : (size_t)a.M;
-    const size_t n = rows * a.cout_p;
+    const size_t n = rows * (size_t)(a.cout_p >> 2);
     const unsigned blocks = (unsigned)((n + 255) / 256);
     switch (dt) {
     case F32: hipLaunchKernelGGL(splitk_reduce<F32>, dim3(blocks), dim3(256), 0, s, a); break;
