@@ -196,11 +196,24 @@ constexpr int ABS_CHUNKS = 64, ABS_THREADS = 256;
 __global__ void __launch_bounds__(ABS_THREADS) absmean_chunks(const float *g, size_t per_image, double *part)
 {
     __shared__ double red[ABS_THREADS];
-    const size_t chunk = (per_image + ABS_CHUNKS - 1) / ABS_CHUNKS;
-    const size_t b = blockIdx.x * chunk, e = min(per_image, b + chunk);
     const float *gi = g + (size_t)blockIdx.y * per_image;
     double s = 0.0;
-    for (size_t k = b + threadIdx.x; k < e; k += ABS_THREADS) s += fabs((double)gi[k]);
+    if (per_image % 4 == 0) {  // 16-byte loads: chunks of whole float4s
+        const size_t q = per_image / 4, chunk = (q + ABS_CHUNKS - 1) / ABS_CHUNKS;
+        const size_t b = blockIdx.x * chunk, e = min(q, b + chunk);
+        const float4 *g4 = reinterpret_cast<const float4 *>(gi);
+        for (size_t k = b + threadIdx.x; k < e; k += ABS_THREADS) {
+            const float4 v = g4[k];
+            s += fabs((double)v.x);
+            s += fabs((double)v.y);
+            s += fabs((double)v.z);
+            s += fabs((double)v.w);
+        }
+    } else {
+        const size_t chunk = (per_image + ABS_CHUNKS - 1) / ABS_CHUNKS;
+        const size_t b = blockIdx.x * chunk, e = min(per_image, b + chunk);
+        for (size_t k = b + threadIdx.x; k < e; k += ABS_THREADS) s += fabs((double)gi[k]);
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = ABS_THREADS / 2; off > 0; off >>= 1) {
@@ -218,6 +231,25 @@ __global__ void absmean_final(const double *part, size_t per_image, double *out)
     out[blockIdx.x] = s / (double)per_image;
 }
 
+__device__ __forceinline__ float ascend1(float x, float g, float step) { return fminf(fmaxf(x + step * g, 0.0f), 1.0f); }
+
+// per_image % 4 == 0: one thread per float4 (a float4 never straddles two images)
+__global__ void __launch_bounds__(256) ascend4(float4 *x, const float4 *g, const double *mean_abs, size_t per_image4,
+                                               size_t total4, float rate)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total4) return;
+    const double m = mean_abs[t / per_image4];
+    const float step = m > 0.0 ? (float)((double)rate / m) : 0.0f;
+    float4 v = x[t];
+    const float4 d = g[t];
+    v.x = ascend1(v.x, d.x, step);
+    v.y = ascend1(v.y, d.y, step);
+    v.z = ascend1(v.z, d.z, step);
+    v.w = ascend1(v.w, d.w, step);
+    x[t] = v;
+}
+
 __global__ void __launch_bounds__(256) ascend(float *x, const float *g, const double *mean_abs, size_t per_image,
                                               size_t total, float rate)
 {
@@ -225,7 +257,7 @@ __global__ void __launch_bounds__(256) ascend(float *x, const float *g, const do
     if (t >= total) return;
     const double m = mean_abs[t / per_image];
     const float step = m > 0.0 ? (float)((double)rate / m) : 0.0f;
-    x[t] = fminf(fmaxf(x[t] + step * g[t], 0.0f), 1.0f);
+    x[t] = ascend1(x[t], g[t], step);
 }
 
 hipError_t launch_leaky_bwd(int dt, const void *a, const void *dy, void *dx, float slope, size_t count, hipStream_t s)
@@ -289,8 +321,14 @@ hipError_t launch_ascend(float *x, const float *g, double *scratch, int n, size_
     hipLaunchKernelGGL(absmean_chunks, dim3(ABS_CHUNKS, n), dim3(ABS_THREADS), 0, s, g, per_image, part);
     hipLaunchKernelGGL(absmean_final, dim3(n), dim3(64), 0, s, part, per_image, mean_abs);
     const size_t total = (size_t)n * per_image;
-    hipLaunchKernelGGL(ascend, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, g, mean_abs, per_image,
-                       total, rate);
+    if (per_image % 4 == 0 && ((uintptr_t)x & 15) == 0 && ((uintptr_t)g & 15) == 0) {
+        const size_t total4 = total / 4;
+        hipLaunchKernelGGL(ascend4, dim3((unsigned)((total4 + 255) / 256)), dim3(256), 0, s, (float4 *)x,
+                           (const float4 *)g, mean_abs, per_image / 4, total4, rate);
+    } else {
+        hipLaunchKernelGGL(ascend, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, g, mean_abs, per_image,
+                           total, rate);
+    }
     return hipGetLastError();
 }
 
