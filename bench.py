@@ -314,6 +314,8 @@ def main():
 
     if args.nightmare_driver:
         n5, a5 = build_net(dn, torch, net, dn.BF16, B, H, W, params, use_graph=False, tune=False)
+        n5.autotune_backward(len(net.layers) - 1, B, H, W, stream)
+        torch.cuda.synchronize()
         for _ in range(6):
             n5.nightmare(len(net.layers) - 1, x, B, H, W, 0.01, 1, stream)
         torch.cuda.synchronize()
@@ -527,6 +529,7 @@ def main():
             n5, a5 = build_net(dn, torch, net, dt, B, H, W, params, use_graph=False, tune=False)
             xn = x.clone()
             last = len(net.layers) - 1
+            n5.autotune_backward(last, B, H, W, stream)
             run = lambda: n5.nightmare(last, xn, B, H, W, 0.01, 1, stream)
             with torch.cuda.stream(stream):
                 wn, pn = time_steps(torch, run, 5, 1, stream)

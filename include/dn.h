@@ -273,6 +273,14 @@ dn_status dn_leaky_backward(int dtype, size_t count, const void *a, const void *
 dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
                             void *stream);
 
+/* Tile autotuner of the input-gradient pass for (layer, batch, h, w): times
+ * every candidate tile configuration x split-K of each unfused forward conv
+ * and each backward-data conv of the pass (hipEvents, synchronous on
+ * `stream`) and keeps the fastest, like dn_autotune (same $DN_TUNE_CACHE).
+ * It uses the pass's library-owned buffer plus 512 MB of candidate scratch.
+ * Optional: untuned convs use the library's heuristic. */
+dn_status dn_autotune_backward(dn_net *net, int layer, int batch, int h, int w, void *stream);
+
 /* `iters` steps of gradient ascent on E with respect to the image, in place:
  * x = clamp(x + rate * g / mean|g|, 0, 1), mean |g| per image (a step of
  * `rate` in the mean absolute sense).  Same buffers and rules as

@@ -1450,7 +1450,8 @@ extern "C" dn_status dn_egress(int dtype, int batch, int c, int h, int w, const 
 // The backward-data conv of forward conv `f`, as a forward conv over the
 // (spread, when f is strided) output gradient: in_c = f.cout, cout = f.in_c,
 // stride 1, pad k-1-pad, linear, bias 0.  hz x wz is its input size.
-static dn_status bwd_desc(const dn_conv_desc *f, int accumulate, dn_conv_desc *b, int *ho, int *wo, int *hz, int *wz)
+static dn_status bwd_desc(const dn_conv_desc *f, int accumulate, dn_conv_desc *b, int *ho, int *wo, int *hz, int *wz,
+                          int tile = -1, int splits = 0)
 {
     if (!f) return fail(DN_EINVAL, "conv desc is NULL");
     if (f->dtype != DN_F32 && f->dtype != DN_BF16) return fail(DN_EUNSUPPORTED, "backward: F32 and BF16 only");
@@ -1473,8 +1474,23 @@ static dn_status bwd_desc(const dn_conv_desc *f, int accumulate, dn_conv_desc *b
     b->tile = -1; b->splits = 0;
     ConvArgs a;
     STCHK(conv_geometry(b, &a, nullptr, nullptr, nullptr, nullptr, nullptr));
-    if (halo_ok(f->dtype, a)) b->tile = HALO_TILE;
+    if (tile >= 0) {  // an explicit (tuned) choice
+        if (tile == HALO_TILE && !halo_ok(f->dtype, a)) return fail(DN_EUNSUPPORTED, "backward: halo tile does not fit");
+        b->tile = tile;
+        b->splits = tile == HALO_TILE ? 1 : std::max(1, splits);
+    } else if (halo_ok(f->dtype, a)) {
+        b->tile = HALO_TILE;
+    }
     return DN_OK;
+}
+
+// Tune-cache key of the backward-data conv of forward conv f.
+static std::string bwd_sig(const dn_conv_desc *f, int accumulate)
+{
+    char k[256];
+    snprintf(k, sizeof k, "bwd_dt%d_b%d_H%d_W%d_ci%d_co%d_R%d_s%d_p%d_a%d", f->dtype, f->batch, f->in_h, f->in_w, f->in_c,
+             f->cout, f->ksize, f->stride, f->pad, accumulate);
+    return k;
 }
 
 // Scratch of a backward-data conv: split-K partials, then the spread gradient.
@@ -1539,11 +1555,12 @@ extern "C" dn_status dn_conv_pack_backward(const dn_conv_desc *d, const double *
 // Enqueue dx (+)= backward-data conv of dy, scratch = [split-K | spread gradient].
 static dn_status enqueue_conv_backward(const dn_conv_desc *f, const void *dy, const void *w_packed,
                                        const float *zero_bias, const float *unit_scale, int accumulate, void *dx,
-                                       void *scratch, size_t scratch_bytes, hipStream_t s)
+                                       void *scratch, size_t scratch_bytes, hipStream_t s, int tile = -1,
+                                       int splits = 0)
 {
     dn_conv_desc b;
     int ho, wo, hz, wz;
-    STCHK(bwd_desc(f, accumulate, &b, &ho, &wo, &hz, &wz));
+    STCHK(bwd_desc(f, accumulate, &b, &ho, &wo, &hz, &wz, tile, splits));
     size_t ws = 0, z = 0;
     STCHK(bwd_scratch(f, &b, hz, wz, &ws, &z));
     if (ws + z > 0 && (!scratch || scratch_bytes < ws + z))
@@ -1555,14 +1572,14 @@ static dn_status enqueue_conv_backward(const dn_conv_desc *f, const void *dy, co
         src = zb;
     }
     ConvArgs a;
-    int tile = 0, splits = 1;
-    STCHK(conv_geometry(&b, &a, &tile, &splits, nullptr, nullptr, nullptr));
+    int use_tile = 0, use_splits = 1;
+    STCHK(conv_geometry(&b, &a, &use_tile, &use_splits, nullptr, nullptr, nullptr));
     a.x = src; a.w = w_packed; a.bias = zero_bias; a.wscale = unit_scale;
     a.res = accumulate ? dx : nullptr;
     a.y = dx;
     a.partial = (float *)scratch;
-    HIPCHK(launch_conv(f->dtype, tile, a, s));
-    if (splits > 1) HIPCHK(launch_splitk_reduce(f->dtype, a, s));
+    HIPCHK(launch_conv(f->dtype, use_tile, a, s));
+    if (use_splits > 1) HIPCHK(launch_splitk_reduce(f->dtype, a, s));
     return DN_OK;
 }
 
@@ -1607,6 +1624,8 @@ struct BwdPlan {
     std::vector<size_t> goff, gbytes;  // gradient of each value 0..seed
     std::vector<dn_conv_desc> fwd;   // per op: the forward conv as a standalone desc (convs only)
     std::vector<char> pool_leaky;    // per op: this pool applies the leaky gradient of its input's producer
+    std::vector<char> acc;           // per op: its input's gradient already holds a contribution (add, not write)
+    std::vector<std::pair<int, int>> btile;  // per conv op: backward (tile, splits); (-1, 0) = heuristic
     size_t bws_off = 0, bws_bytes = 0;  // backward conv scratch
     size_t gin_off = 0, mabs_off = 0;   // NCHW FP32 input gradient, per-image mean |g|
     size_t total = 0;
@@ -1652,6 +1671,19 @@ static dn_status make_bwd_plan(const dn_net *net, int target, int batch, int h, 
             net->L[prev.conv].activation == DN_ACT_LEAKY)
             b.pool_leaky[k] = 1;
     }
+    // which gradient writes add to an earlier contribution (the reverse walk's order)
+    b.acc.assign(b.nops, 0);
+    {
+        std::vector<char> have(b.seed + 1, 0);
+        have[b.seed] = 1;
+        for (int k = b.nops - 1; k >= 0; --k) {
+            const Op &op = p.ops[k];
+            b.acc[k] = have[op.in];
+            have[op.in] = 1;
+            if (op.kind == OP_ADD) have[op.in2] = 1;
+        }
+    }
+    b.btile.assign(b.nops, {-1, 0});
     size_t bws = 0;
     for (int k = 0; k < b.nops; ++k) {
         const Op &op = p.ops[k];
@@ -1663,9 +1695,11 @@ static dn_status make_bwd_plan(const dn_net *net, int target, int batch, int h, 
         f.cout = d.cout; f.ksize = d.ksize; f.stride = d.stride; f.pad = d.pad;
         f.activation = d.activation; f.leaky_slope = net->o.leaky_slope; f.dtype = dt;
         f.in_scale = f.res_scale = f.out_scale = 1.0f; f.tile = -1;
+        auto it = net->tuned.find(bwd_sig(&f, b.acc[k]));
+        if (it != net->tuned.end()) b.btile[k] = it->second;
         dn_conv_desc bd;
         int ho, wo, hz, wz;
-        STCHK(bwd_desc(&f, 1, &bd, &ho, &wo, &hz, &wz));
+        STCHK(bwd_desc(&f, b.acc[k], &bd, &ho, &wo, &hz, &wz, b.btile[k].first, b.btile[k].second));
         size_t ws = 0, z = 0;
         STCHK(bwd_scratch(&f, &bd, hz, wz, &ws, &z));
         bws = std::max(bws, ws + z);
@@ -1691,7 +1725,7 @@ static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, cha
     for (int k = 0; k < b.nops; ++k) STCHK(enqueue_op(net, p, p.ops[k], base, s, false, -1, 0, x));
     // objective: half the sum of squares of the seed layer's output -> its gradient is the output itself
     HIPCHK(hipMemcpyAsync(base + b.goff[b.seed], base + p.vals[b.seed].off, b.gbytes[b.seed], hipMemcpyDeviceToDevice, s));
-    std::vector<char> have(b.seed + 1, 0);
+    std::vector<char> have(b.seed + 1, 0);  // shortcut inputs: copy first, add after
     have[b.seed] = 1;
     for (int k = b.nops - 1; k >= 0; --k) {
         const Op &op = p.ops[k];
@@ -1704,14 +1738,14 @@ static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, cha
             const bool masked = k + 1 < b.nops && b.pool_leaky[k + 1];  // the pool after it applied the leaky gradient
             if (d.activation == DN_ACT_LEAKY && !masked)
                 HIPCHK(launch_leaky_bwd(dt, base + vo.off, gout, gout, net->o.leaky_slope, count, s));
-            STCHK(enqueue_conv_backward(&b.fwd[k], gout, cw.wb, cw.bzero, cw.bscale, have[op.in], base + b.goff[op.in],
-                                        base + b.bws_off, b.bws_bytes, s));
+            STCHK(enqueue_conv_backward(&b.fwd[k], gout, cw.wb, cw.bzero, cw.bscale, b.acc[k], base + b.goff[op.in],
+                                        base + b.bws_off, b.bws_bytes, s, b.btile[k].first, b.btile[k].second));
             have[op.in] = 1;
         } else if (op.kind == OP_POOL) {
             const dn_layer_desc &d = net->L[op.layer];
             const Value &vi = p.vals[op.in];
             HIPCHK(launch_maxpool_bwd(dt, base + vi.off, gout, base + b.goff[op.in], p.batch, vi.h, vi.w, vi.cp, d.ksize,
-                                      d.stride, vo.h, vo.w, have[op.in], b.pool_leaky[k] ? net->o.leaky_slope : -1.0f, s));
+                                      d.stride, vo.h, vo.w, b.acc[k], b.pool_leaky[k] ? net->o.leaky_slope : -1.0f, s));
             have[op.in] = 1;
         } else {
             for (int src : {op.in, op.in2}) {
@@ -1726,26 +1760,26 @@ static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, cha
     return DN_OK;
 }
 
-static dn_status bwd_prepare(dn_net *net, int layer, const void *x, int batch, int h, int w, BwdPlan *b)
+static dn_status bwd_prepare(dn_net *net, int layer, int batch, int h, int w, BwdPlan *b, size_t extra = 0)
 {
     if (net->o.dtype != DN_F32 && net->o.dtype != DN_BF16)
         return fail(DN_EUNSUPPORTED, "input gradient: F32 and BF16 nets only");
     STCHK(check_ready(net, false));
     STCHK(check_dims(net, batch, h, w));
-    if (!x) return fail(DN_EINVAL, "x is NULL");
     for (size_t i = 0; i < net->L.size(); ++i)
         if (net->L[i].kind == DN_CONV && !net->cw[i].wb) return fail(DN_ESTATE, "conv layer %zu has no backward weights", i);
     STCHK(make_bwd_plan(net, layer, batch, h, w, b));
+    const size_t need = b->total + extra;
     std::lock_guard<std::mutex> g(net->mu);
-    if (net->bwd_bytes < b->total) {
+    if (net->bwd_bytes < need) {
         if (net->bwd_buf) {
             HIPCHK(hipDeviceSynchronize());
             HIPCHK(hipFree(net->bwd_buf));
             net->bwd_buf = nullptr;
             net->bwd_bytes = 0;
         }
-        HIPCHK(hipMalloc(&net->bwd_buf, b->total));
-        net->bwd_bytes = b->total;
+        HIPCHK(hipMalloc(&net->bwd_buf, need));
+        net->bwd_bytes = need;
     }
     return DN_OK;
 }
@@ -1755,9 +1789,10 @@ extern "C" dn_status dn_input_gradient(dn_net *net, int layer, const float *x, i
 {
     if (!net) return fail(DN_EINVAL, "net is NULL");
     if (!grad) return fail(DN_EINVAL, "grad is NULL");
+    if (!x) return fail(DN_EINVAL, "x is NULL");
     HIPCHK(hipSetDevice(net->o.device));
     BwdPlan b;
-    STCHK(bwd_prepare(net, layer, x, batch, h, w, &b));
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)net->bwd_buf;
     STCHK(enqueue_input_gradient(net, b, base, x, s));
@@ -1772,9 +1807,10 @@ extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, i
     if (!net) return fail(DN_EINVAL, "net is NULL");
     if (iters < 0) return fail(DN_EINVAL, "iters must be >= 0");
     if (!std::isfinite(rate)) return fail(DN_EINVAL, "rate must be finite");
+    if (!x) return fail(DN_EINVAL, "x is NULL");
     HIPCHK(hipSetDevice(net->o.device));
     BwdPlan b;
-    STCHK(bwd_prepare(net, layer, x, batch, h, w, &b));
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)net->bwd_buf;
     for (int it = 0; it < iters; ++it) {
@@ -1783,6 +1819,130 @@ extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, i
                              (size_t)net->o.in_c * h * w, rate, s));
     }
     return DN_OK;
+}
+
+// Time `launch` (which enqueues one candidate) 1 + 5 times; the mean of the last 5 in ms, or a status.
+template <typename F> static dn_status time_candidate(F launch, hipEvent_t e0, hipEvent_t e1, hipStream_t s, float *ms)
+{
+    for (int rep = 0; rep < 2; ++rep) {  // rep 0 = warm-up
+        const int iters = rep ? 5 : 1;
+        HIPCHK(hipEventRecord(e0, s));
+        for (int it = 0; it < iters; ++it) STCHK(launch());
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        if (rep) {
+            HIPCHK(hipEventElapsedTime(ms, e0, e1));
+            *ms /= iters;
+        }
+    }
+    return DN_OK;
+}
+
+constexpr size_t BWD_TUNE_SCRATCH = (size_t)512 << 20;
+
+static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int w, hipStream_t s, hipEvent_t e0,
+                                   hipEvent_t e1)
+{
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b, BWD_TUNE_SCRATCH));
+    char *base = (char *)net->bwd_buf;
+    char *scratch = base + b.total;  // candidate split-K partials (and spread gradients) go here
+    Plan p = b.p;
+    p.ws_off = b.total;
+    const int dt = p.dtype;
+    // the unfused forward convs (first-layer kernel excepted): same candidates as dn_autotune
+    for (int k = 0; k < b.nops; ++k) {
+        const Op &op = p.ops[k];
+        if (op.kind != OP_CONV || op.first) continue;
+        const dn_layer_desc &d = net->L[op.conv];
+        const std::string sig = conv_sig(dt, op, batch, d.ksize, d.stride);
+        if (net->tuned.count(sig)) continue;
+        const int M = batch * op.Ho * op.Wo;
+        const int nkt = net->cw[op.conv].k_pad / bk_el(dt);
+        std::vector<int> cands;
+        if (op_halo_ok(net, dt, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
+        for (int t = 0; t < tile_count(); ++t)
+            if (tile_fits(t, op.cout_p)) cands.push_back(t);
+        float best = 1e30f;
+        int bt = op.tile, bs = op.splits;
+        for (int t : cands) {
+            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
+            const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
+            for (int sp = 1; sp <= 16; sp *= 2) {
+                if (t == HALO_TILE && sp > 1) break;
+                if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
+                if (sp > 1 && (size_t)sp * M * op.cout_p * 4 > BWD_TUNE_SCRATCH) continue;
+                float ms = 0.f;
+                STCHK(time_candidate([&] { return enqueue_op(net, p, op, base, s, false, t, sp); }, e0, e1, s, &ms));
+                if (ms < best) { best = ms; bt = t; bs = sp; }
+            }
+        }
+        std::lock_guard<std::mutex> g(net->mu);
+        net->tuned[sig] = {bt, bs};
+    }
+    // the backward-data convs
+    for (int k = 0; k < b.nops; ++k) {
+        const Op &op = p.ops[k];
+        if (op.kind != OP_CONV) continue;
+        const dn_conv_desc &f = b.fwd[k];
+        const std::string sig = bwd_sig(&f, b.acc[k]);
+        if (net->tuned.count(sig)) continue;
+        const ConvWeights &cw = net->cw[op.conv];
+        dn_conv_desc bd;
+        int ho, wo, hz, wz;
+        STCHK(bwd_desc(&f, b.acc[k], &bd, &ho, &wo, &hz, &wz));
+        ConvArgs a;
+        STCHK(conv_geometry(&bd, &a, nullptr, nullptr, nullptr, nullptr, nullptr));
+        const int nkt = a.k_pad / bk_el(dt);
+        std::vector<int> cands;
+        if (halo_ok(dt, a)) cands.push_back(HALO_TILE);
+        for (int t = 0; t < tile_count(); ++t)
+            if (tile_fits(t, a.cout_p)) cands.push_back(t);
+        float best = 1e30f;
+        std::pair<int, int> bt{-1, 0};
+        for (int t : cands) {
+            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
+            const long tiles = (long)((a.M + tc.bm - 1) / tc.bm) * ((a.cout_p + tc.bn - 1) / tc.bn);
+            for (int sp = 1; sp <= 16; sp *= 2) {
+                if (t == HALO_TILE && sp > 1) break;
+                if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
+                dn_conv_desc cd;
+                int h2, w2, hz2, wz2;
+                STCHK(bwd_desc(&f, b.acc[k], &cd, &h2, &w2, &hz2, &wz2, t, sp));
+                size_t ws = 0, z = 0;
+                STCHK(bwd_scratch(&f, &cd, hz2, wz2, &ws, &z));
+                if (ws + z > BWD_TUNE_SCRATCH) continue;
+                float ms = 0.f;
+                STCHK(time_candidate([&] {
+                    return enqueue_conv_backward(&f, base + b.goff[op.out], cw.wb, cw.bzero, cw.bscale, b.acc[k],
+                                                 base + b.goff[op.in], scratch, BWD_TUNE_SCRATCH, s, t, sp);
+                }, e0, e1, s, &ms));
+                if (ms < best) { best = ms; bt = {t, sp}; }
+            }
+        }
+        std::lock_guard<std::mutex> g(net->mu);
+        net->tuned[sig] = bt;
+    }
+    return DN_OK;
+}
+
+extern "C" dn_status dn_autotune_backward(dn_net *net, int layer, int batch, int h, int w, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    HIPCHK(hipSetDevice(net->o.device));
+    load_tune_cache(net);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const dn_status rc = autotune_backward(net, layer, batch, h, w, (hipStream_t)stream, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == DN_OK) {
+        std::lock_guard<std::mutex> g(net->mu);
+        save_tune_cache(net);
+        drop_graphs(net);
+    }
+    return rc;
 }
 
 extern "C" int dn_tile_count(void) { return tile_count(); }

@@ -101,6 +101,7 @@ SIGNATURES = {
     "dn_leaky_backward": (_i, [_i, _sz, _vp, _vp, _f, _vp, _vp]),
     "dn_input_gradient": (_i, [_vp, _i, _vp, _i, _i, _i, _vp, _vp]),
     "dn_nightmare": (_i, [_vp, _i, _vp, _i, _i, _i, _f, _i, _vp]),
+    "dn_autotune_backward": (_i, [_vp, _i, _i, _i, _i, _vp]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -304,6 +305,9 @@ class Net:
 
     def input_gradient(self, layer: int, x, batch: int, h: int, w: int, grad, stream=None) -> None:
         check(LIB.dn_input_gradient(self._h, layer, ptr(x), batch, h, w, ptr(grad), stream_handle(stream)))
+
+    def autotune_backward(self, layer: int, batch: int, h: int, w: int, stream=None) -> None:
+        check(LIB.dn_autotune_backward(self._h, layer, batch, h, w, stream_handle(stream)))
 
     def nightmare(self, layer: int, x, batch: int, h: int, w: int, rate: float, iters: int, stream=None) -> None:
         check(LIB.dn_nightmare(self._h, layer, ptr(x), batch, h, w, rate, iters, stream_handle(stream)))

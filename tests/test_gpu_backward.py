@@ -245,6 +245,29 @@ def test_input_gradient_parity(dn, dtype, case):
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_input_gradient_after_backward_autotune(dn, dtype):
+    """Tuned tiles (split-K, accumulating epilogues, halo) for every conv of
+    the pass, forward and backward, give the same gradient within the gates."""
+    torch = G.torch_cuda()
+    net = synth.residual52(units=(1, 2), widths=(64, 128), in_hw=32)
+    n, h, w, seed, layer = 2, 32, 32, 37, 11
+    params = synth.make_params(net, seed)
+    x = synth.make_input(net, n, seed, h=h, w=w)
+    gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype)
+    gn.load_params(params)
+    gn.autotune_backward(layer, n, h, w)
+    xd = G.dev(x.astype(np.float32))
+    g = torch.empty_like(xd)
+    gn.input_gradient(layer, xd, n, h, w, g)
+    torch.cuda.synchronize()
+    got = g.cpu().numpy().astype(np.float64)
+    ref = _ref_gradient(net, dtype, params, x, layer)
+    err, gate = G.rel_l2(got, ref), _gate(net, dtype, params, x, layer, ref)
+    print("tuned input gradient %s rel_l2=%.3e gate %.3e" % (G.NAME[dtype], err, gate))
+    assert err < gate
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
 def test_nightmare_step_parity(dn, dtype):
     torch = G.torch_cuda()
     net = _small_net()
