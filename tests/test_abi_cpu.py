@@ -145,6 +145,13 @@ def test_backward_op_validation_without_gpu(dn):
     assert e.value.status == dn.DN_EINVAL
 
 
+def test_backward_net_calls_reject_null_without_gpu(dn):
+    assert dn.LIB.dn_input_gradient(None, 0, None, 1, 8, 8, None, None) == dn.DN_EINVAL
+    assert dn.LIB.dn_nightmare(None, 0, None, 1, 8, 8, 0.1, 1, None) == dn.DN_EINVAL
+    assert dn.LIB.dn_autotune_backward(None, 0, 1, 8, 8, None) == dn.DN_EINVAL
+    assert dn.last_error()
+
+
 def test_leaky_shortcut_rejected(dn):
     import synth
     layers = [synth.conv(16, 3), synth.conv(16, 3), synth.Layer(synth.SHORTCUT, src=0, activation=synth.LEAKY)]
