@@ -15,6 +15,9 @@
 //                 leaky gradient of the layer that produced the pool's input
 //                 (that layer's output is the pool's input, so its sign is at
 //                 hand), saving a pass over the largest tensors
+//   unpool_bwd    the gradient through a pool fused into its conv: the conv's
+//                 epilogue stored each window's argmax code, so the full-size
+//                 conv output never has to be kept
 //   dilate        spreads a stride-s output gradient onto the stride-1 grid
 //                 (zeros between), so a strided conv's backward-data is a
 //                 stride-1 conv over the spread gradient
@@ -170,6 +173,50 @@ __global__ void __launch_bounds__(256) maxpool_bwd(const void *x, const void *dy
     ((uint4 *)dx)[t] = Seg<DT>::enc(g);
 }
 
+// One thread per pooled (pixel, 16-byte segment): E argmax codes, the pooled
+// values (their sign is the sign of the window's maximal conv output) and the
+// output gradient in, the four segments of the 2x2 window out.
+template <int DT>
+__global__ void __launch_bounds__(256) unpool_bwd(const unsigned char *argmax, const void *pooled, const void *dy,
+                                                  void *dz, int n, int hp, int wp, int cp, float mask)
+{
+    constexpr int E = Seg<DT>::N;
+    const int nseg = cp / E;
+    const size_t total = (size_t)n * hp * wp * nseg;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int sg = (int)(t % nseg);
+    const size_t p = t / nseg;
+    const int j = (int)(p % wp);
+    const size_t q = p / wp;
+    const int i = (int)(q % hp);
+    const int img = (int)(q / hp);
+    float a[E], d[E];
+    Seg<DT>::dec(((const uint4 *)pooled)[t], a);
+    Seg<DT>::dec(((const uint4 *)dy)[t], d);
+    unsigned char am[E];
+    if constexpr (E == 4) {
+        const unsigned v = reinterpret_cast<const unsigned *>(argmax)[t];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) am[e] = (unsigned char)(v >> (8 * e));
+    } else {
+        const uint2 v = reinterpret_cast<const uint2 *>(argmax)[t];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { am[e] = (unsigned char)(v.x >> (8 * e)); am[e + 4] = (unsigned char)(v.y >> (8 * e)); }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) d[e] *= leaky_factor(a[e], mask);
+    const int w = 2 * wp, h = 2 * hp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float g[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) g[e] = am[e] == k ? d[e] : 0.0f;
+        const size_t o = (((size_t)img * h + 2 * i + (k >> 1)) * w + 2 * j + (k & 1)) * nseg + sg;
+        ((uint4 *)dz)[o] = Seg<DT>::enc(g);
+    }
+}
+
 __global__ void __launch_bounds__(256) dilate(const uint4 *dy, uint4 *z, int n, int ho, int wo, int nseg, int hz, int wz,
                                               int stride)
 {
@@ -296,6 +343,20 @@ hipError_t launch_maxpool_bwd(int dt, const void *x, const void *dy, void *dx, i
     switch (dt) {
     case F32: hipLaunchKernelGGL(maxpool_bwd<F32>, g, b, 0, s, x, dy, dx, n, h, w, cp, size, stride, ho, wo, accumulate, mask); break;
     case BF16: hipLaunchKernelGGL(maxpool_bwd<BF16>, g, b, 0, s, x, dy, dx, n, h, w, cp, size, stride, ho, wo, accumulate, mask); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpool_bwd(int dt, const unsigned char *argmax, const void *pooled, const void *dy, void *dz, int n,
+                             int hp, int wp, int cp, float mask, hipStream_t s)
+{
+    const size_t total = (size_t)n * hp * wp * (cp / seg_el(dt));
+    if (total == 0) return hipSuccess;
+    dim3 g((unsigned)((total + 255) / 256)), b(256);
+    switch (dt) {
+    case F32: hipLaunchKernelGGL(unpool_bwd<F32>, g, b, 0, s, argmax, pooled, dy, dz, n, hp, wp, cp, mask); break;
+    case BF16: hipLaunchKernelGGL(unpool_bwd<BF16>, g, b, 0, s, argmax, pooled, dy, dz, n, hp, wp, cp, mask); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

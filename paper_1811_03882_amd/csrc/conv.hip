@@ -155,6 +155,31 @@ __device__ __forceinline__ float activate(float v, int act, float slope)
     return v > 0.0f ? v : v * slope;
 }
 
+// The value an output takes once stored (rounded to the storage type).
+template <int DT> __device__ __forceinline__ float stored_value(float v)
+{
+    if constexpr (DT == F32) return v;
+    else if constexpr (DT == BF16) return bf2f(f2bf(v));
+    else return e4m32f(f2e4m3(v));
+}
+
+// Index (2*dy + dx) of the first maximal stored output of a 2x2 window whose
+// accumulators are acc[0..3] in row-major window order: the branch the
+// max-pool gradient follows.
+// The output is activate(acc * scl + bias) * post, as in the caller's epilogue.
+template <int DT> __device__ __forceinline__ unsigned char window_argmax(const float *acc, float scl, float bias,
+                                                                        int act, float slope, float post)
+{
+    int k = 0;
+    float m = stored_value<DT>(activate(acc[0] * scl + bias, act, slope) * post);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+        const float o = stored_value<DT>(activate(acc[q] * scl + bias, act, slope) * post);
+        if (o > m) { m = o; k = q; }
+    }
+    return (unsigned char)k;
+}
+
 // ---------------------------------------------------------------- the kernel
 
 // Global-memory accesses go through explicit address-space-1 pointers so that
@@ -212,6 +237,10 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][F
                 // rounding are monotone
                 const float mx = fmaxf(fmaxf(acc[fm][fn][0], acc[fm][fn][1]), fmaxf(acc[fm][fn][2], acc[fm][fn][3]));
                 store_el<DT>(a.y, (size_t)(mb >> 2) * a.cout_p + col, activate(mx * scl + bias, a.act, a.slope) * a.out_inv_scale);
+                if (a.argmax) {
+                    const float w4[4] = {acc[fm][fn][0], acc[fm][fn][1], acc[fm][fn][2], acc[fm][fn][3]};
+                    a.argmax[(size_t)(mb >> 2) * a.cout_p + col] = window_argmax<DT>(w4, scl, bias, a.act, a.slope, a.out_inv_scale);
+                }
             } else {
                 float v[4];
 #pragma unroll
@@ -672,15 +701,23 @@ __global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
     };
     float o[4], t[4];
     if (a.pool) {
+        float w4[4][4];  // [column][window element]
 #pragma unroll
         for (int j = 0; j < 4; ++j) o[j] = -INFINITY;
         for (int q = 0; q < 4; ++q) {
             total(ro * 4 + q, t);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) o[j] = fmaxf(o[j], activate(t[j] * scl[j] + bias[j], a.act, a.slope));
+            for (int j = 0; j < 4; ++j) {
+                w4[j][q] = t[j];
+                o[j] = fmaxf(o[j], activate(t[j] * scl[j] + bias[j], a.act, a.slope));
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
+        if (a.argmax) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a.argmax[ro * a.cout_p + col + j] = window_argmax<DT>(w4[j], scl[j], bias[j], a.act, a.slope, a.out_inv_scale);
+        }
     } else {
         total(ro, t);
 #pragma unroll
@@ -923,7 +960,14 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
                 const float o = activate(mx * scl4[nb][0] + bias4[nb][0], a.act, a.slope) * opost;
                 const int hp = (th0 >> 1) + (bho >> 1), wp = (tw0 >> 1) + (bwo >> 1) + lgrp;
-                if (hp < Hy && col < a.cout_p && wp < Wy) store_el<DT>(yimg, (hp * Wy + wp) * a.cout_p + col, o);
+                if (hp < Hy && col < a.cout_p && wp < Wy) {
+                    store_el<DT>(yimg, (hp * Wy + wp) * a.cout_p + col, o);
+                    if (a.argmax) {
+                        const float w4[4] = {acc[0], acc[1], acc[2], acc[3]};
+                        a.argmax[(size_t)n * Hy * Wy * a.cout_p + (hp * Wy + wp) * a.cout_p + col] =
+                            window_argmax<DT>(w4, scl4[nb][0], bias4[nb][0], a.act, a.slope, opost);
+                    }
+                }
             } else {
                 // acc[i]: channel ch0 + i of this lane's pixel
 #pragma unroll
@@ -1184,7 +1228,13 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
                 const float o = activate(mx * scl + bias, a.act, a.slope) * a.out_inv_scale;
                 const int rp = b / (HT_W / 8), wg = b % (HT_W / 8);
                 const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
-                if (hp < Hp && wp < Wp) store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
+                if (hp < Hp && wp < Wp) {
+                    store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
+                    if (a.argmax) {
+                        const float w4[4] = {acc[i][nb][0], acc[i][nb][1], acc[i][nb][2], acc[i][nb][3]};
+                        a.argmax[(size_t)n * img + (hp * Wp + wp) * a.cout_p + col] = window_argmax<DT>(w4, scl, bias, a.act, a.slope, a.out_inv_scale);
+                    }
+                }
             } else {
                 float v[4];
 #pragma unroll

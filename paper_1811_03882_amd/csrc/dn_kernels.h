@@ -53,6 +53,9 @@ struct ConvArgs {
     float in_scale, res_scale, out_inv_scale;  // FP8 scales (1 otherwise)
     int splits, ktiles_per_split;
     unsigned x_bytes, w_bytes;  // buffer sizes (set by the launcher)
+    // fused pool only, may be nullptr: per pooled output element, the index
+    // 2*dy + dx of the first maximal stored value of its 2x2 window
+    unsigned char *argmax;
 };
 
 // First convolution of a network, reading the NCHW FP32 input directly.
@@ -69,6 +72,7 @@ struct FirstArgs {
     float in_inv_scale;    // FP8: 1 / input scale (else 1)
     float in_scale, out_inv_scale;
     int th;                // output rows per tile (set by launch_conv_first)
+    unsigned char *argmax; // pool = 1 only, may be nullptr: as ConvArgs::argmax
 };
 // Channels of one staged window pixel: C rounded up to 4, 8 or 16.
 __host__ __device__ constexpr int first_cp(int C) { return C <= 4 ? 4 : (C <= 8 ? 8 : 16); }
@@ -122,6 +126,11 @@ hipError_t launch_leaky_bwd(int dt, const void *a, const void *dy, void *dx, flo
 // mask >= 0 also multiplies by the leaky gradient of x (1 where x > 0, else mask).
 hipError_t launch_maxpool_bwd(int dt, const void *x, const void *dy, void *dx, int n, int h, int w, int cp, int size,
                               int stride, int ho, int wo, int accumulate, float mask, hipStream_t s);
+// Gradient of a conv output through its fused 2x2/2 pool: dz[n][2i+dy][2j+dx][c] =
+// dy[n][i][j][c] * (leaky gradient from the pooled output's sign, mask >= 0) where
+// argmax[n][i][j][c] == 2*dy + dx, else 0; every element of dz is written.
+hipError_t launch_unpool_bwd(int dt, const unsigned char *argmax, const void *pooled, const void *dy, void *dz, int n,
+                             int hp, int wp, int cp, float mask, hipStream_t s);
 // z[n][hz][wz][cp] = dy[n][i/stride][j/stride] where stride divides i and j, else 0.
 hipError_t launch_dilate(int dt, const void *dy, void *z, int n, int ho, int wo, int cp, int hz, int wz, int stride,
                          hipStream_t s);

@@ -94,6 +94,8 @@ struct Op {
     int c_log = 0;       // logical channels of the output
     int tile = -1, splits = 1;
     size_t ws_bytes = 0;
+    bool argmax = false;  // fused pool: also store each window's argmax (input-gradient pass)
+    size_t argmax_off = 0;
 };
 
 struct Value { int c = 0, cp = 0, h = 0, w = 0; size_t bytes = 0, off = 0; int first = 0, last = 0; };
@@ -237,6 +239,7 @@ static ConvArgs conv_args(const dn_net *net, const Plan &p, const Op &op, char *
     a.res = op.res ? base + p.vals[op.in2].off : nullptr;
     a.y = base + p.vals[op.out].off;
     a.partial = (float *)(base + p.ws_off);
+    a.argmax = op.argmax ? (unsigned char *)(base + op.argmax_off) : nullptr;
     a.batch = p.batch;
     a.H = op.H; a.W = op.W; a.cin_p = op.cin_p;
     a.Ho = op.pool ? op.Ho * 2 : op.Ho;
@@ -273,7 +276,11 @@ static bool op_halo_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
     return halo_ok(dtype, a);
 }
 
-static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, int h, int w, Plan *out)
+// pool_fuse_upto >= 0 (input-gradient pass, per-layer mode otherwise): fuse a
+// conv with the 2x2/2 pool after it when that pool's layer index is at most
+// pool_fuse_upto; no residual fusion.
+static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, int h, int w, Plan *out,
+                           int pool_fuse_upto = -1)
 {
     const int n = (int)net->L.size();
     if (batch <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "batch/h/w must be positive (%d, %d, %d)", batch, h, w);
@@ -328,14 +335,16 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
             op.H = p.vals[i].h; op.W = p.vals[i].w; op.cin_p = p.vals[i].cp;
             op.Ho = p.vals[i + 1].h; op.Wo = p.vals[i + 1].w;
             op.cout = d.cout; op.cout_p = p.vals[i + 1].cp;
-            if (mode == DN_MODE_RESIDENT && i + 1 < n && uses[i + 1] == 1) {
+            const bool fuse = mode == DN_MODE_RESIDENT || (pool_fuse_upto >= 0 && i + 1 <= pool_fuse_upto);
+            if (fuse && i + 1 < n && uses[i + 1] == 1) {
                 const dn_layer_desc &nx = net->L[i + 1];
                 if (nx.kind == DN_MAXPOOL && nx.ksize == 2 && nx.stride == 2 && op.Ho % 2 == 0 && op.Wo % 2 == 0) {
                     op.pool = true;
                     op.layer = i + 1; op.out = i + 2;
                     op.Ho /= 2; op.Wo /= 2;
                     ++i;
-                } else if (nx.kind == DN_SHORTCUT && nx.src != i && nx.activation == DN_ACT_LINEAR) {
+                } else if (mode == DN_MODE_RESIDENT && nx.kind == DN_SHORTCUT && nx.src != i &&
+                           nx.activation == DN_ACT_LINEAR) {
                     op.res = true;
                     op.in2 = nx.src + 1;
                     op.layer = i + 1; op.out = i + 2;
@@ -454,6 +463,7 @@ static dn_status enqueue_first(const dn_net *net, const Plan &p, const Op &op, c
     a.k_pad = first_kpad(use32 ? (int)F32 : p.dtype, d.ksize);
     a.R = a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
     a.pool = op.pool ? 1 : 0;
+    a.argmax = op.argmax ? (unsigned char *)(base + op.argmax_off) : nullptr;
     a.act = d.activation;
     a.slope = net->o.leaky_slope;
     a.in_inv_scale = a.in_scale = a.out_inv_scale = 1.0f;
@@ -1637,14 +1647,28 @@ static dn_status make_bwd_plan(const dn_net *net, int target, int batch, int h, 
     if (dt != DN_F32 && dt != DN_BF16) return fail(DN_EUNSUPPORTED, "input gradient: F32 and BF16 nets only");
     if (target < 0 || target >= (int)net->L.size()) return fail(DN_EINVAL, "layer %d out of range", target);
     BwdPlan b;
-    STCHK(make_plan(net, dt, DN_MODE_PER_LAYER, batch, h, w, &b.p));
+    STCHK(make_plan(net, dt, DN_MODE_PER_LAYER, batch, h, w, &b.p, target));
     Plan &p = b.p;
-    b.nops = target + 1;  // unfused: op i computes layer i
+    b.nops = 0;  // ops computing layers 0..target (a conv with its fused pool is one op)
+    while (b.nops < (int)p.ops.size() && p.ops[b.nops].layer <= target) ++b.nops;
     b.seed = target + 1;
+    if (b.nops == 0 || p.ops[b.nops - 1].out != b.seed) return fail(DN_EINVAL, "layer %d: no op ends there", target);
+    // every produced value keeps its own buffer (the full-size output of a conv
+    // with a fused pool is never stored: its windows' argmax codes are)
+    std::vector<char> produced(b.seed + 1, 0);
+    produced[0] = 1;
+    for (int k = 0; k < b.nops; ++k) produced[p.ops[k].out] = 1;
     size_t off = 0;
     for (int v = 0; v <= b.seed; ++v) {
         p.vals[v].off = off;
-        off += p.vals[v].bytes;
+        if (produced[v]) off += p.vals[v].bytes;
+    }
+    for (int k = 0; k < b.nops; ++k) {
+        Op &op = p.ops[k];
+        if (op.kind != OP_CONV || !op.pool) continue;
+        op.argmax = true;
+        op.argmax_off = off;
+        off += align256((size_t)batch * op.Ho * op.Wo * op.cout_p);
     }
     p.ws_off = align256(off);
     off = p.ws_off + align256(p.ws_bytes);
@@ -1732,7 +1756,19 @@ static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, cha
         char *gout = base + b.goff[op.out];
         const Value &vo = p.vals[op.out];
         const size_t count = (size_t)p.batch * vo.h * vo.w * vo.cp;
-        if (op.kind == OP_CONV) {
+        if (op.kind == OP_CONV && op.pool) {
+            // fused 2x2/2 pool: each window's gradient goes to its argmax element,
+            // times the leaky gradient there (the pooled output has its sign)
+            const dn_layer_desc &d = net->L[op.conv];
+            const ConvWeights &cw = net->cw[op.conv];
+            char *gfull = base + b.goff[op.conv + 1];
+            HIPCHK(launch_unpool_bwd(dt, (const unsigned char *)(base + op.argmax_off), base + vo.off, gout, gfull,
+                                     p.batch, op.Ho, op.Wo, op.cout_p,
+                                     d.activation == DN_ACT_LEAKY ? net->o.leaky_slope : -1.0f, s));
+            STCHK(enqueue_conv_backward(&b.fwd[k], gfull, cw.wb, cw.bzero, cw.bscale, b.acc[k], base + b.goff[op.in],
+                                        base + b.bws_off, b.bws_bytes, s, b.btile[k].first, b.btile[k].second));
+            have[op.in] = 1;
+        } else if (op.kind == OP_CONV) {
             const dn_layer_desc &d = net->L[op.conv];
             const ConvWeights &cw = net->cw[op.conv];
             const bool masked = k + 1 < b.nops && b.pool_leaky[k + 1];  // the pool after it applied the leaky gradient
@@ -1857,7 +1893,7 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         const dn_layer_desc &d = net->L[op.conv];
         const std::string sig = conv_sig(dt, op, batch, d.ksize, d.stride);
         if (net->tuned.count(sig)) continue;
-        const int M = batch * op.Ho * op.Wo;
+        const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
         const int nkt = net->cw[op.conv].k_pad / bk_el(dt);
         std::vector<int> cands;
         if (op_halo_ok(net, dt, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
@@ -1913,9 +1949,11 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
                 STCHK(bwd_scratch(&f, &cd, hz2, wz2, &ws, &z));
                 if (ws + z > BWD_TUNE_SCRATCH) continue;
                 float ms = 0.f;
+                // the gradient of the full-size conv output (for a fused pool: the unpooled one)
+                char *gy = base + b.goff[op.pool ? op.conv + 1 : op.out];
                 STCHK(time_candidate([&] {
-                    return enqueue_conv_backward(&f, base + b.goff[op.out], cw.wb, cw.bzero, cw.bscale, b.acc[k],
-                                                 base + b.goff[op.in], scratch, BWD_TUNE_SCRATCH, s, t, sp);
+                    return enqueue_conv_backward(&f, gy, cw.wb, cw.bzero, cw.bscale, b.acc[k], base + b.goff[op.in],
+                                                 scratch, BWD_TUNE_SCRATCH, s, t, sp);
                 }, e0, e1, s, &ms));
                 if (ms < best) { best = ms; bt = {t, sp}; }
             }
