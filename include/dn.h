@@ -264,8 +264,10 @@ dn_status dn_leaky_backward(int dtype, size_t count, const void *a, const void *
 
 /* Gradient with respect to the input image of E = 1/2 * sum of squares of
  * layer `layer`'s output over the batch.  x, grad: device NCHW FP32
- * [batch][in_c][h][w].  Runs the forward up to `layer` unfused, keeping every
- * layer output, then each layer's backward in reverse order (gradients of a
+ * [batch][in_c][h][w].  Runs the forward up to `layer` keeping every layer
+ * output (a conv and the 2x2/2 pool after it run fused and keep the pooled
+ * output plus each window's argmax code instead of the full-size conv
+ * output), then each layer's backward in reverse order (gradients of a
  * shortcut's two inputs add up).  Needs every conv's weights loaded
  * (DN_ESTATE).  The library keeps one device buffer per net for this pass,
  * grown on demand (hipMalloc outside any capture) and freed by
