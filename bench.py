@@ -179,9 +179,11 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print)
             **out}
 
 
-def traffic_from_profiles(layer_key: str):
+def traffic_from_profiles(layer_key: str, tile: int):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    PMC summary, only if it was taken on the current kernel source."""
+    PMC summary, only if it was taken on the current kernel source and with
+    the tile configuration this run chose (the autotuner may pick either of
+    two near-equal tiles from run to run; the summary holds one entry each)."""
     path = os.path.join(ROOT, "profiles", "conv_dominant_b64_bf16_hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -190,7 +192,7 @@ def traffic_from_profiles(layer_key: str):
             d = json.load(f)
         if d.get("kernel_source_hash") != kernel_source_hash():
             return None
-        return d.get(layer_key, {}).get("hbm_bytes_per_launch")
+        return d.get(layer_key, {}).get("tile%d" % tile, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError):
         return None
 
@@ -229,7 +231,7 @@ def summarize_trace(trace_csv: str, min_run: int = 20) -> str:
     return "\n".join(out)
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, launches: int = 5):
+def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, tile: int, launches: int = 5):
     """HBM bytes per launch of the dominant conv from two rocprofv3 --pmc runs
     of `bench.py --pmc-driver` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
     Each counter is scaled by what it reads for the driver's 256 MiB device
@@ -255,8 +257,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, launches: int = 5)
                         "bytes_per_launch": float(np.mean([v for _, v in kern])) * 1024.0 / factor}
     total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
     return {"kernel_source_hash": kernel_source_hash(),
-            "layer%d" % layer: {"kernel": res["FETCH_SIZE"]["kernel"], "hbm_bytes_per_launch": total,
-                                "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"]}}
+            "layer%d" % layer: {"tile%d" % tile: {"kernel": res["FETCH_SIZE"]["kernel"], "hbm_bytes_per_launch": total,
+                                                  "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"]}}}
 
 
 def main():
@@ -275,15 +277,16 @@ def main():
                     help="run only 5 image-modification steps (BF16, batch 64, 416x416), for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print a markdown summary of a rocprofv3 --kernel-trace CSV and exit (no GPU)")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER"),
-                    help="print the HBM-traffic JSON of two --pmc-driver counter runs and exit (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER", "TILE"),
+                    help="print the HBM-traffic JSON of two --pmc-driver counter runs (the dominant conv on "
+                         "tile config TILE, as the driver printed it) and exit (no GPU)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
         return
     if args.summarize_pmc:
-        f, w, layer = args.summarize_pmc
-        print(json.dumps(summarize_pmc(f, w, int(layer)), indent=1))
+        f, w, layer, tile = args.summarize_pmc
+        print(json.dumps(summarize_pmc(f, w, int(layer), int(tile)), indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: inference is data-parallel with no per-forward exchange, "
@@ -363,7 +366,7 @@ def main():
             % (li, M, N, K, plan["tile"], plan["splits"], ms, per_layer[li]["tflops"], per_layer[li]["mfma_pct"]))
     achieved = flops[dom][0] / (dom_ms * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["bf16"], "traffic": traffic_from_profiles("layer%d" % dom),
+                "frac": achieved / PEAK["bf16"], "traffic": traffic_from_profiles("layer%d" % dom, per_layer[dom]["tile"]),
                 "kernel": "conv layer %d bf16, tile config %d (%s): conv3x3 1024->1024 on 13x13, M=%d N=%d K=%d"
                           % (dom, per_layer[dom]["tile"], _tile_desc(dn, per_layer[dom]["tile"]), *flops[dom][1:]),
                 "avg_launch_ms": dom_ms}

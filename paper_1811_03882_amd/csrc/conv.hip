@@ -788,7 +788,9 @@ template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned cha
 }
 
 
-template <int DT, bool POOL, int CP>
+// AM (with POOL): also store each window's argmax code (a.argmax); a template
+// flag so that the forward's own instantiations carry none of that code.
+template <int DT, bool POOL, int CP, bool AM = false>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 {
     constexpr int ES = esize(DT), SEG = seg_el(DT);
@@ -962,7 +964,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 const int hp = (th0 >> 1) + (bho >> 1), wp = (tw0 >> 1) + (bwo >> 1) + lgrp;
                 if (hp < Hy && col < a.cout_p && wp < Wy) {
                     store_el<DT>(yimg, (hp * Wy + wp) * a.cout_p + col, o);
-                    if (a.argmax) {
+                    if constexpr (AM) {
                         const float w4[4] = {acc[0], acc[1], acc[2], acc[3]};
                         a.argmax[(size_t)n * Hy * Wy * a.cout_p + (hp * Wy + wp) * a.cout_p + col] =
                             window_argmax<DT>(w4, scl4[nb][0], bias4[nb][0], a.act, a.slope, opost);
@@ -1006,23 +1008,29 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
         a.stride > 2 || (a.cout_p & 3) || (size_t)a.Ho * a.Wo * a.cout_p >= (1u << 31))
         return hipErrorInvalidValue;
     dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + b.th - 1) / b.th, a.batch);
-#define DN_FIRST_CP(D, P, C)                                                                         \
+#define DN_FIRST_CP(D, P, C, M)                                                                      \
     do {                                                                                             \
-        allow_lds(conv_first<D, P, C>, lds);                                                         \
-        hipLaunchKernelGGL((conv_first<D, P, C>), grid, dim3(256), lds, s, b);                       \
+        allow_lds(conv_first<D, P, C, M>, lds);                                                      \
+        hipLaunchKernelGGL((conv_first<D, P, C, M>), grid, dim3(256), lds, s, b);                    \
     } while (0)
-#define DN_FIRST_P(D, P)                                                                             \
+#define DN_FIRST_P(D, P, M)                                                                          \
     do {                                                                                             \
         const int cp = first_cp(a.C);                                                                \
-        if (cp == 4) DN_FIRST_CP(D, P, 4);                                                           \
-        else if (cp == 8) DN_FIRST_CP(D, P, 8);                                                      \
-        else DN_FIRST_CP(D, P, 16);                                                                  \
+        if (cp == 4) DN_FIRST_CP(D, P, 4, M);                                                        \
+        else if (cp == 8) DN_FIRST_CP(D, P, 8, M);                                                   \
+        else DN_FIRST_CP(D, P, 16, M);                                                               \
     } while (0)
 #define DN_FIRST(D)                                                                                  \
     do {                                                                                             \
-        if (b.pool) DN_FIRST_P(D, true);                                                             \
-        else DN_FIRST_P(D, false);                                                                   \
+        if (b.pool) DN_FIRST_P(D, true, false);                                                      \
+        else DN_FIRST_P(D, false, false);                                                            \
     } while (0)
+    if (b.argmax && (!b.pool || dt == FP8)) return hipErrorInvalidValue;
+    if (b.argmax) {  // the input-gradient pass (F32 / BF16)
+        if (dt == F32) DN_FIRST_P(F32, true, true);
+        else DN_FIRST_P(BF16, true, true);
+        return hipGetLastError();
+    }
     switch (dt) {
     case F32: DN_FIRST(F32); break;
     case BF16: DN_FIRST(BF16); break;
@@ -1082,7 +1090,8 @@ bool halo_ok(int dt, const ConvArgs &a)
 }
 
 
-template <int DT, bool POOL, int TH, int NB>
+// AM (with POOL): also store each window's argmax code (a.argmax).
+template <int DT, bool POOL, int TH, int NB, bool AM = false>
 __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
 {
     constexpr int ES = esize(DT), SEG = seg_el(DT);
@@ -1230,7 +1239,7 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
                 const int hp = (th0 >> 1) + rp, wp = (tw0 >> 1) + wg * 4 + lgrp;
                 if (hp < Hp && wp < Wp) {
                     store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
-                    if (a.argmax) {
+                    if constexpr (AM) {
                         const float w4[4] = {acc[i][nb][0], acc[i][nb][1], acc[i][nb][2], acc[i][nb][3]};
                         a.argmax[(size_t)n * img + (hp * Wp + wp) * a.cout_p + col] = window_argmax<DT>(w4, scl, bias, a.act, a.slope, a.out_inv_scale);
                     }
@@ -1256,14 +1265,14 @@ __global__ void __launch_bounds__(256) conv_halo(ConvArgs a)
     }
 }
 
-template <int DT, bool POOL, int TH>
+template <int DT, bool POOL, int TH, bool AM = false>
 static hipError_t go_halo(const ConvArgs &a, dim3 grid, size_t lds, hipStream_t s)
 {
     switch ((a.cout_p + 15) / 16) {
-    case 1: allow_lds(conv_halo<DT, POOL, TH, 1>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 1>), grid, dim3(256), lds, s, a); break;
-    case 2: allow_lds(conv_halo<DT, POOL, TH, 2>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 2>), grid, dim3(256), lds, s, a); break;
-    case 3: allow_lds(conv_halo<DT, POOL, TH, 3>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 3>), grid, dim3(256), lds, s, a); break;
-    case 4: allow_lds(conv_halo<DT, POOL, TH, 4>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 4>), grid, dim3(256), lds, s, a); break;
+    case 1: allow_lds(conv_halo<DT, POOL, TH, 1, AM>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 1, AM>), grid, dim3(256), lds, s, a); break;
+    case 2: allow_lds(conv_halo<DT, POOL, TH, 2, AM>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 2, AM>), grid, dim3(256), lds, s, a); break;
+    case 3: allow_lds(conv_halo<DT, POOL, TH, 3, AM>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 3, AM>), grid, dim3(256), lds, s, a); break;
+    case 4: allow_lds(conv_halo<DT, POOL, TH, 4, AM>, lds); hipLaunchKernelGGL((conv_halo<DT, POOL, TH, 4, AM>), grid, dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1272,6 +1281,10 @@ static hipError_t go_halo(const ConvArgs &a, dim3 grid, size_t lds, hipStream_t 
 template <int DT>
 static hipError_t go_halo_dt(const ConvArgs &a, int th, dim3 grid, size_t lds, hipStream_t s)
 {
+    if constexpr (DT != FP8) {
+        if (a.pool && a.argmax)  // the input-gradient pass
+            return th == 16 ? go_halo<DT, true, 16, true>(a, grid, lds, s) : go_halo<DT, true, 8, true>(a, grid, lds, s);
+    }
     if (th == 16) return a.pool ? go_halo<DT, true, 16>(a, grid, lds, s) : go_halo<DT, false, 16>(a, grid, lds, s);
     return a.pool ? go_halo<DT, true, 8>(a, grid, lds, s) : go_halo<DT, false, 8>(a, grid, lds, s);
 }
