@@ -105,7 +105,7 @@ def test_plain9_bf16_b64_graph_sampled(dn):
     net = synth.plain9()
     params = synth.make_params(net, synth.SEED_PLAIN)
     x = synth.make_input(net, 64, synth.SEED_PLAIN)
-    n = make_net(dn, net, dn.BF16, 64, 416, 416, use_graph=True)
+    n = make_net(dn, net, dn.BF16, 64, 416, 416, use_graph=True, tune=True)  # the bench's configuration
     shape = n.output_shape(416, 416)
     xd = G.dev(x.astype(np.float32))
     y = torch.empty((64,) + shape, dtype=torch.float32, device="cuda")
@@ -134,6 +134,29 @@ def test_plain9_bf16_b64_graph_sampled(dn):
     err = G.rel_l2(alone, got[5:6])
     print("batch invariance image 5 rel diff = %.3e" % err)
     assert err < 2e-2
+
+
+def test_plain9_fp8_b64_tuned_graph_sampled(dn):
+    """The FP8 configuration the bench times (batch 64, 416x416, calibrated,
+    autotuned, graph): sampled images against the oracle (end-to-end FP8 error
+    is reported, not gated: the per-layer gates hold, see the test below), and
+    the batch-64 result of one image against that image run alone (different
+    tiles and split-K) within the FP8 gate."""
+    torch = G.torch_cuda()
+    net = synth.plain9()
+    params = synth.make_params(net, synth.SEED_PLAIN)
+    x = synth.make_input(net, 64, synth.SEED_PLAIN)
+    n = make_net(dn, net, dn.FP8, 64, 416, 416, use_graph=True, tune=True)
+    shape = n.output_shape(416, 416)
+    got = gpu_forward(dn, n, x, shape)
+    assert np.all(np.isfinite(got))
+    for i in (0, 63):
+        ref = onet.forward(net, params, x[i:i + 1])[-1]
+        print("plain9 fp8 b64 image %d rel_l2 = %.3e (reported)" % (i, G.rel_l2(got[i:i + 1], ref)))
+    alone = gpu_forward(dn, n, x[9:10], shape)
+    err = G.rel_l2(alone, got[9:10])
+    print("fp8 batch invariance image 9 rel diff = %.3e" % err)
+    assert err < G.GATE[2]
 
 
 def test_plain9_fp8_per_layer_gates_and_end_to_end(dn):
