@@ -11,6 +11,10 @@
  * every intermediate activation stays in a device arena, and the output
  * crosses once.  The per-layer mode copies each layer's input, weights and
  * output around its kernel, the naive per-loop offload that Sec. 3.2 removes.
+ * Beside the forward: the backward pass to the input image and the image
+ * ascent of the image-edit program (dn_input_gradient, dn_nightmare), the
+ * detection post-processing (dn_detect) and the paper's second sample program,
+ * Jacobi iteration for the Laplace equation (dn_jacobi).
  *
  * Conventions for every function:
  *   - returns dn_status (0 = DN_OK, negative = error); never throws or aborts;

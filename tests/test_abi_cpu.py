@@ -180,3 +180,18 @@ def test_detect_workspace_and_validation(dn):
     with pytest.raises(dn.DnError) as e:                            # NULL buffers are refused before any launch
         dn.detect(None, 1, 5, 20, 13, 13, [1.0] * 10, 0.2, 0.45, 10, None, 0, None, None, None)
     assert e.value.status == dn.DN_EINVAL
+
+
+def test_committed_traffic_profile_is_well_formed():
+    """The dominant conv's HBM traffic summary (read by bench.py) holds one
+    entry per tile config, each above the 63.2 MB the kernel must move."""
+    import json
+    path = os.path.join(ROOT, "profiles", "conv_dominant_b64_bf16_hbm_traffic.json")
+    d = json.load(open(path))
+    assert len(d["kernel_source_hash"]) == 16
+    entries = d["layer13"]
+    assert entries and all(k.startswith("tile") for k in entries)
+    for e in entries.values():
+        assert e["hbm_bytes_per_launch"] > 63.2e6
+        assert abs(e["fetch"]["factor"] - 0.5) < 0.01 and abs(e["write"]["factor"] - 1.0) < 0.01
+        assert e["kernel"].startswith("void dnk::conv_igemm_dl<1,")
