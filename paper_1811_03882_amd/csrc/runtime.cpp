@@ -2,7 +2,9 @@
 // library: layer-list validation, the execution plan with its fusions, the
 // liveness-packed activation arena, weight upload / FP64 fold, the resident
 // and per-layer-transfer forwards, hipGraph capture/replay, FP8 calibration
-// and the tile autotuner.
+// and the tile autotuner; the backward pass to the input image and the image
+// ascent (with their own plan and autotuner), the standalone layer and
+// backward ops, detection post-processing and the Jacobi/Laplace iteration.
 //
 // Transfer placement follows the rule of Sec. 3.2 of the paper: a copy is
 // placed outside the outermost loop that does not define (host->device) or
