@@ -83,6 +83,8 @@ BWD_SHAPES = [
     (3, 9, 11, 32, 125, 1, 1, 0, False),    # 1x1 from 125 channels (padded)
     (1, 8, 8, 256, 96, 3, 1, 1, True),      # long K: channel-block K order, split-K
     (2, 6, 5, 1024, 512, 3, 1, 1, True),    # 9-layer net's 1024-wide layers on a small map
+    (1, 1, 1, 16, 32, 3, 1, 1, True),       # 1x1 map: every tap but the centre lies in the padding
+    (1, 2, 3, 8, 8, 3, 2, 1, True),         # tiny ragged stride 2 (output 1x2)
 ]
 
 
@@ -111,6 +113,18 @@ def test_conv_backward_data_accumulates(dn, dtype):
     assert G.rel_l2(got, ref) < G.GATE[dtype]
 
 
+def test_backward_rejects_empty_batch(dn):
+    d = dn.conv_desc(0, 8, 8, 16, 16, 3, 1, 1, dn.LEAKY, 0.1, 0, 0, dn.F32)
+    with pytest.raises(dn.DnError) as e:
+        dn.conv_backward_sizes(d)
+    assert e.value.status == dn.DN_EINVAL
+    torch = G.torch_cuda()
+    buf = torch.zeros(64, device="cuda")
+    with pytest.raises(dn.DnError) as e:
+        dn.maxpool_backward(0, 4, 4, 8, 2, 2, dn.F32, buf, buf, 0, buf)
+    assert e.value.status == dn.DN_EINVAL
+
+
 def test_conv_backward_rejects_fused_and_fp8(dn):
     d = dn.conv_desc(1, 8, 8, 16, 16, 3, 1, 1, dn.LEAKY, 0.1, 2, 0, dn.F32)
     with pytest.raises(dn.DnError) as e:
@@ -123,7 +137,8 @@ def test_conv_backward_rejects_fused_and_fp8(dn):
 
 
 # n, h, w, c, size, stride
-POOL_BWD = [(2, 8, 10, 16, 2, 2), (1, 7, 9, 24, 2, 2), (2, 13, 13, 32, 2, 1), (1, 9, 8, 8, 3, 2), (1, 5, 6, 3, 3, 1)]
+POOL_BWD = [(2, 8, 10, 16, 2, 2), (1, 7, 9, 24, 2, 2), (2, 13, 13, 32, 2, 1), (1, 9, 8, 8, 3, 2), (1, 5, 6, 3, 3, 1),
+            (1, 1, 1, 8, 2, 2), (1, 1, 3, 8, 2, 1)]  # windows that reach past a 1-pixel-high input
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
