@@ -275,6 +275,9 @@ def main():
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     ap.add_argument("--nightmare-driver", action="store_true",
                     help="run only 5 image-modification steps (BF16, batch 64, 416x416), for a kernel trace")
+    ap.add_argument("--residual-driver", action="store_true",
+                    help="run only 20 graph forwards of the 52-layer residual net (BF16, batch 16, 256x256), "
+                         "for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print a markdown summary of a rocprofv3 --kernel-trace CSV and exit (no GPU)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER", "TILE"),
@@ -315,6 +318,17 @@ def main():
     stream = torch.cuda.Stream()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
 
+    if args.residual_driver:
+        rnet = synth.residual52()
+        rparams = synth.make_params(rnet, synth.SEED_RESIDUAL)
+        xr = torch.from_numpy(synth.make_input(rnet, 16, synth.SEED_RESIDUAL).astype(np.float32)).cuda()
+        n6, a6 = build_net(dn, torch, rnet, dn.BF16, 16, 256, 256, params=rparams)
+        yr = torch.empty((16,) + n6.output_shape(256, 256), device="cuda")
+        for _ in range(20):
+            n6.forward(xr, 16, 256, 256, yr, stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"residual_driver": True, "forwards": 20, "batch": 16}))
+        return
     if args.nightmare_driver:
         n5, a5 = build_net(dn, torch, net, dn.BF16, B, H, W, params, use_graph=False, tune=False)
         n5.autotune_backward(len(net.layers) - 1, B, H, W, stream)
