@@ -218,12 +218,12 @@ class Scheduler:
 
     # -- admission
     def _pick(self):
+        """(size, candidate requests, queue they come from) of the bucket whose
+        oldest request has waited longest, or None."""
         if not self.bucketed:
             if not self.fifo:
                 return None
-            head = self.fifo[0]
-            reqs = [head]
-            return head.size, reqs, lambda: self.fifo.popleft()
+            return self.fifo[0].size, [self.fifo[0]], self.fifo
         best = None
         for s, q in self.queues.items():
             if q and (best is None or q[0].arrival < self.queues[best][0].arrival):
@@ -231,8 +231,10 @@ class Scheduler:
         if best is None:
             return None
         q = self.queues[best]
-        reqs = list(q)[: self.max_batch]
-        return best, reqs, lambda: [q.popleft() for _ in range(len(reqs))]
+        return best, list(q)[: self.max_batch], q
+
+    def _padded(self, n: int) -> int:
+        return min(next_pow2(n) if self.pad_pow2 else n, self.max_batch)
 
     def admit(self) -> int:
         launched = 0
@@ -240,14 +242,22 @@ class Scheduler:
             pick = self._pick()
             if pick is None:
                 break
-            size, reqs, pop = pick
-            padded = next_pow2(len(reqs)) if self.pad_pow2 else len(reqs)
-            padded = min(padded, self.max_batch)
+            size, reqs, queue = pick
+            padded = self._padded(len(reqs))
             nbytes = self.ex.batch_bytes(padded, size)
             off = self.pool.alloc(nbytes)
+            # Nothing in flight means no completion will free memory: take
+            # fewer requests (halving) until the padded batch fits.  One image
+            # always fits an idle pool (submit() rejected anything larger).
+            while off is None and not self.inflight and len(reqs) > 1:
+                reqs = reqs[: (len(reqs) + 1) // 2]
+                padded = self._padded(len(reqs))
+                nbytes = self.ex.batch_bytes(padded, size)
+                off = self.pool.alloc(nbytes)
             if off is None:
                 break  # over budget: wait for completions
-            pop()
+            for _ in range(len(reqs)):
+                queue.popleft()
             slot = self.free_slots.pop(0)
             b = Batch(slot, size, padded, reqs, off, nbytes, self.clock())
             try:

@@ -167,3 +167,26 @@ def test_plain_fifo_path_batch_one():
     assert st.completed == 100 and st.mean_batch == 1.0 and sch.max_inflight == 1
     order = [ids[0] for _, _, _, _, ids in ex.log]
     assert order == sorted(order)  # arrival order (ids follow the trace order)
+
+
+def test_padded_batch_over_budget_on_an_idle_pool_shrinks_instead_of_waiting():
+    # the budget holds a padded batch of 2 at S=320: three requests pad to 4,
+    # which never fits; with nothing in flight the scheduler must split them
+    clk = Clock()
+    ex = FakeExecutor(clk, n_slots=4)
+    sch = Scheduler(ex, budget_bytes=ex.batch_bytes(2, 320), sizes=(320,), clock=clk)
+    reqs = [Request(i, 320, 0.0) for i in range(3)]
+    st = sch.run(reqs)
+    assert st.completed == 3 and st.failed == 0 and st.rejected == 0
+    assert sorted(len(ids) for _, _, _, _, ids in ex.log) == [1, 2]
+    for r in reqs:
+        assert r.output[0] == r.rid
+
+
+def test_budget_of_one_image_serves_a_burst_one_by_one():
+    clk = Clock()
+    ex = FakeExecutor(clk, n_slots=2)
+    sch = Scheduler(ex, budget_bytes=ex.batch_bytes(1, 608), sizes=(608,), clock=clk)
+    st = sch.run([Request(i, 608, 0.0) for i in range(9)])
+    assert st.completed == 9 and sch.max_inflight == 1
+    assert all(len(ids) == 1 for _, _, _, _, ids in ex.log)
