@@ -332,6 +332,8 @@ def main():
     if args.nightmare_driver:
         n5, a5 = build_net(dn, torch, net, dn.BF16, B, H, W, params, use_graph=False, tune=False)
         n5.autotune_backward(len(net.layers) - 1, B, H, W, stream)
+        ga = torch.empty(n5.input_gradient_arena_bytes(len(net.layers) - 1, B, H, W), dtype=torch.uint8, device="cuda")
+        n5.bind_arena(ga)
         torch.cuda.synchronize()
         for _ in range(6):
             n5.nightmare(len(net.layers) - 1, x, B, H, W, 0.01, 1, stream)
@@ -547,6 +549,8 @@ def main():
             xn = x.clone()
             last = len(net.layers) - 1
             n5.autotune_backward(last, B, H, W, stream)
+            ga = torch.empty(n5.input_gradient_arena_bytes(last, B, H, W), dtype=torch.uint8, device="cuda")
+            n5.bind_arena(ga)
             run = lambda: n5.nightmare(last, xn, B, H, W, 0.01, 1, stream)
             with torch.cuda.stream(stream):
                 wn, pn = time_steps(torch, run, 5, 1, stream)
@@ -558,7 +562,7 @@ def main():
                               "conv_pct_peak": 100.0 * 2 * fl_all / (ms * 1e-3) / PEAK[name]})
             log("[bench] nightmare %s: %.3f ms per step" % (name, ms))
             n5.close()
-            del a5, xn
+            del a5, xn, ga
 
         # FP32 plain path, batch 1: resident (graph) vs per-layer transfers
         x1 = x[:1].contiguous()

@@ -273,26 +273,56 @@ dn_status dn_leaky_backward(int dtype, size_t count, const void *a, const void *
  * output plus each window's argmax code instead of the full-size conv
  * output), then each layer's backward in reverse order (gradients of a
  * shortcut's two inputs add up).  Needs every conv's weights loaded
- * (DN_ESTATE).  The library keeps one device buffer per net for this pass,
- * grown on demand (hipMalloc outside any capture) and freed by
- * dn_net_destroy; calls on one net must not overlap.  Enqueue only. */
+ * (DN_ESTATE).  Every buffer of the pass (stored layer outputs, argmax codes,
+ * gradients, scratch) lives in the caller's arena: the one bound with
+ * dn_bind_arena, which must hold at least dn_input_gradient_arena_bytes
+ * (else DN_ENOMEM; none bound: DN_ESTATE).  No allocation, no host
+ * synchronisation: enqueue only.  Calls that share an arena must not overlap
+ * (same stream, or ordered by the caller); dn_input_gradient_arena takes an
+ * explicit arena (256-byte aligned device memory) so that passes on disjoint
+ * arenas may run concurrently. */
+dn_status dn_input_gradient_arena_bytes(const dn_net *net, int layer, int batch, int h, int w, size_t *bytes);
 dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
                             void *stream);
+dn_status dn_input_gradient_arena(dn_net *net, void *arena, size_t arena_bytes, int layer, const float *x,
+                                  int batch, int h, int w, float *grad, void *stream);
+
+/* Read back what the last input-gradient pass on `arena` (same net, layer,
+ * batch, h, w) left there, into caller device memory `out` (out_bytes), on
+ * `stream`; for inspecting the branches the pass took (tests):
+ *   what = 0: the stored output of layer of_layer (0 <= of_layer <= layer),
+ *             NCHW FP32 [batch][c][ho][wo]; not stored for a conv whose
+ *             2x2/2 pool ran fused (*available = 0);
+ *   what = 1: the argmax codes of pool layer of_layer when it ran fused with
+ *             the conv before it: uint8 NHWC [batch][ho][wo][c padded], code
+ *             2*dy + dx of the window element that received the gradient;
+ *   what = 2: the gradient of E with respect to layer of_layer's output
+ *             (for a conv with a fused pool: its full-size output), NCHW FP32.
+ * *available (may be NULL) tells whether the pass keeps that buffer; with
+ * out = NULL only *available is set.  Enqueue only. */
+dn_status dn_input_gradient_readback(const dn_net *net, void *arena, size_t arena_bytes, int layer, int batch,
+                                     int h, int w, int of_layer, int what, void *out, size_t out_bytes,
+                                     int *available, void *stream);
 
 /* Tile autotuner of the input-gradient pass for (layer, batch, h, w): times
  * every candidate tile configuration x split-K of each unfused forward conv
  * and each backward-data conv of the pass (hipEvents, synchronous on
  * `stream`) and keeps the fastest, like dn_autotune (same $DN_TUNE_CACHE).
- * It uses the pass's library-owned buffer plus 512 MB of candidate scratch.
+ * A tuning call: it allocates a temporary device buffer (the pass's arena
+ * plus 512 MB of candidate scratch) and frees it before returning.
  * Optional: untuned convs use the library's heuristic. */
 dn_status dn_autotune_backward(dn_net *net, int layer, int batch, int h, int w, void *stream);
 
 /* `iters` steps of gradient ascent on E with respect to the image, in place:
  * x = clamp(x + rate * g / mean|g|, 0, 1), mean |g| per image (a step of
  * `rate` in the mean absolute sense).  Same buffers and rules as
- * dn_input_gradient; no host round-trip between iterations. */
+ * dn_input_gradient (bound arena, or the explicit one of dn_nightmare_arena,
+ * of at least dn_input_gradient_arena_bytes); no host round-trip between
+ * iterations, no allocation. */
 dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, int h, int w, float rate, int iters,
                        void *stream);
+dn_status dn_nightmare_arena(dn_net *net, void *arena, size_t arena_bytes, int layer, float *x, int batch, int h,
+                             int w, float rate, int iters, void *stream);
 
 /* ---- Jacobi iteration for the Laplace equation: the second program the
  * paper's transfer rule sped up (Sec. 4, the paragraph before Sec. 5).

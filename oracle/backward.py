@@ -25,15 +25,19 @@ back through the layers 0..L one at a time:
 One ascent step: x' = clip(x + rate * g / mean|g|, 0, 1), mean |g| taken per
 image (left unchanged where g is zero).
 
-``input_gradient_stored`` is the same gradient for the BF16 path's
-definition (stored operands rounded to BF16), so that every branch is taken
-on the same stored values as on the device.
+``input_gradient_on_piece`` is the gradient with the branch decisions (leaky
+signs, pooling window choices) given by the caller: the gradient of the
+piece of the piecewise-linear pass that those decisions select.  The device
+comparison takes the decisions the device took, after checking that each one
+that differs from this oracle's own lies within the forward error of its
+threshold.
 
 Pins: tests/test_oracle_backward.py checks every piece against central
 finite differences of the forward definitions and the adjoint identity of the
 convolution, the step against its closed form on an identity network, the
-stored-operand variant against the plain one when nothing is rounded, and the
-BF16 rounding against hand-worked values.
+BF16 rounding against hand-worked values, and the given-decision gradient
+against ``input_gradient`` when the decisions are the oracle's own and
+against pure-Python brute force on tiny nets with decisions flipped.
 """
 from __future__ import annotations
 
@@ -58,68 +62,6 @@ def round_bf16(a) -> np.ndarray:
 
 def round_f32(a) -> np.ndarray:
     return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
-
-
-def _forward_stored(net: Net, params, x: np.ndarray, layer: int, q, qb):
-    """Forward up to ``layer`` with every stored operand in a storage format:
-    the input image, the BN-folded weights (fold in FP64, then q) and every
-    layer output pass through q; the folded bias through qb; arithmetic is FP64.
-    Returns (layer inputs, layer outputs, stored weights)."""
-    cur = q(x)
-    ins, outs, wq = [], [], {}
-    for i in range(layer + 1):
-        L = net.layers[i]
-        ins.append(cur)
-        if L.kind == CONV:
-            p = params[i]
-            w = np.asarray(p.w, np.float64)
-            b = np.asarray(p.bias, np.float64)
-            if L.batchnorm:
-                sc = np.asarray(p.gamma, np.float64) / np.sqrt(np.asarray(p.var, np.float64) + net.bn_eps)
-                w = w * sc[:, None, None, None]
-                b = (b - np.asarray(p.mean, np.float64)) * sc + np.asarray(p.beta, np.float64)
-            wq[i] = q(w)
-            z = add_bias(conv2d(cur, wq[i], L.stride, L.pad), qb(b))
-            if L.activation == LEAKY:
-                z = np.where(z > 0.0, z, z * net.leaky_slope)
-            cur = q(z)
-        elif L.kind == MAXPOOL:
-            cur = maxpool(cur, L.ksize, L.stride)
-        elif L.kind == SHORTCUT:
-            cur = q(outs[i - 1] + outs[L.src])
-        else:
-            raise ValueError("unknown layer kind %r" % (L.kind,))
-        outs.append(cur)
-    return ins, outs, wq
-
-
-def input_gradient_stored(net: Net, params, x: np.ndarray, layer: int, q=round_bf16, qb=round_f32) -> np.ndarray:
-    """dE/dx of the network whose stored operands are in the format q (the
-    BF16 path's definition: BF16 image, folded weights and activations, FP32
-    bias).  Every branch (leaky sign, first maximum of a pooling window) is
-    taken on the stored activations, as the device takes it; the gradient
-    arithmetic is FP64 with the stored weights."""
-    x = np.ascontiguousarray(x, dtype=np.float64)
-    ins, outs, wq = _forward_stored(net, params, x, layer, q, qb)
-    grads: List[Optional[np.ndarray]] = [None] * (layer + 2)
-
-    def add(v: int, g: np.ndarray) -> None:
-        grads[v] = g if grads[v] is None else grads[v] + g
-
-    grads[layer + 1] = outs[layer].copy()
-    for i in range(layer, -1, -1):
-        L = net.layers[i]
-        gy = grads[i + 1]
-        if L.kind == CONV:
-            if L.activation == LEAKY:
-                gy = gy * np.where(outs[i] > 0.0, 1.0, net.leaky_slope)
-            add(i, conv2d_backward_data(gy, wq[i], L.stride, L.pad, ins[i].shape[2], ins[i].shape[3]))
-        elif L.kind == MAXPOOL:
-            add(i, maxpool_backward(ins[i], L.ksize, L.stride, gy))
-        else:
-            add(i, gy)
-            add(L.src + 1, gy)
-    return grads[0]
 
 
 def energy(net: Net, params: List[Optional[ConvParams]], x: np.ndarray, layer: int) -> float:
@@ -156,6 +98,95 @@ def input_gradient(net: Net, params: List[Optional[ConvParams]], x: np.ndarray, 
             add(i, conv2d_backward_data(gy, p.w, L.stride, L.pad, xin.shape[2], xin.shape[3]))
         elif L.kind == MAXPOOL:
             add(i, maxpool_backward(xin, L.ksize, L.stride, gy))
+        elif L.kind == SHORTCUT:
+            if L.activation == LEAKY:
+                gy = gy * np.where(outs[i] > 0.0, 1.0, net.leaky_slope)
+            add(i, gy)
+            add(L.src + 1, gy)
+        else:
+            raise ValueError("unknown layer kind %r" % (L.kind,))
+    return grads[0]
+
+
+def maxpool_backward_picked(shape, size: int, stride: int, pick: np.ndarray, dy: np.ndarray) -> np.ndarray:
+    """Max-pool gradient with the window decisions given: the gradient of output
+    (n, c, i, j) goes to window element pick[n, c, i, j] = u*size + v, i.e. input
+    (i*stride - o + u, j*stride - o + v) with o = (size - 1)//2 (the window of
+    ``maxpool``).  A pick outside the input is an error."""
+    n, c, h, w = shape
+    pick = np.asarray(pick)
+    dy = np.asarray(dy, np.float64)
+    if pick.shape != dy.shape:
+        raise ValueError("pick shape %s != gradient shape %s" % (pick.shape, dy.shape))
+    off = (size - 1) // 2
+    dx = np.zeros(shape, np.float64)
+    for u in range(size):
+        for v in range(size):
+            nn, cc, i, j = np.nonzero(pick == u * size + v)
+            yy = i * stride - off + u
+            xx = j * stride - off + v
+            if np.any((yy < 0) | (yy >= h) | (xx < 0) | (xx >= w)):
+                raise ValueError("a window's gradient was given to a tap outside the input")
+            np.add.at(dx, (nn, cc, yy, xx), dy[nn, cc, i, j])
+    if np.any((pick < 0) | (pick >= size * size)):
+        raise ValueError("pick outside the window")
+    return dx
+
+
+def input_gradient_on_piece(net: Net, params: List[Optional[ConvParams]], x: np.ndarray, layer: int,
+                            leaky_pass=None, pool_pick=None) -> np.ndarray:
+    """dE/dx with the branch decisions given instead of taken.
+
+    The energy's gradient is piecewise linear in the seed: its pieces are the
+    leaky branches (z > 0 or not) and the max-pool window decisions.  This is
+    ``input_gradient`` with those decisions supplied by the caller, everything
+    else (FP64 forward for the seed, unfolded BN scale, backward-data conv)
+    unchanged:
+
+    * ``leaky_pass[i]`` (conv layer i with a leaky activation): bool array of
+      layer i's output shape, True where the gradient passes unchanged and
+      False where it is scaled by the slope;
+    * ``pool_pick[i]`` (maxpool layer i): int array of the pool's output shape,
+      the window element u*size + v that receives each window's gradient.
+
+    Layers absent from the dicts decide as ``input_gradient`` does."""
+    leaky_pass = leaky_pass or {}
+    pool_pick = pool_pick or {}
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    outs = forward(net, params, x, upto=layer + 1)
+    ins = [x] + outs[:-1]
+    grads: List[Optional[np.ndarray]] = [None] * (layer + 2)
+
+    def add(v: int, g: np.ndarray) -> None:
+        grads[v] = g if grads[v] is None else grads[v] + g
+
+    grads[layer + 1] = outs[layer].copy()
+    for i in range(layer, -1, -1):
+        L = net.layers[i]
+        gy = grads[i + 1]
+        xin = ins[i]
+        if L.kind == CONV:
+            p = params[i]
+            if L.activation == LEAKY:
+                if i in leaky_pass:
+                    passes = np.asarray(leaky_pass[i], bool)
+                    if passes.shape != gy.shape:
+                        raise ValueError("leaky decisions of layer %d: shape %s != %s" % (i, passes.shape, gy.shape))
+                else:
+                    z = add_bias(conv2d(xin, p.w, L.stride, L.pad), p.bias)
+                    if L.batchnorm:
+                        z = batchnorm(z, p.mean, p.var, p.gamma, p.beta, net.bn_eps)
+                    passes = z > 0.0
+                gy = gy * np.where(passes, 1.0, net.leaky_slope)
+            if L.batchnorm:
+                scale = np.asarray(p.gamma, np.float64) / np.sqrt(np.asarray(p.var, np.float64) + net.bn_eps)
+                gy = gy * scale[None, :, None, None]
+            add(i, conv2d_backward_data(gy, p.w, L.stride, L.pad, xin.shape[2], xin.shape[3]))
+        elif L.kind == MAXPOOL:
+            if i in pool_pick:
+                add(i, maxpool_backward_picked(xin.shape, L.ksize, L.stride, pool_pick[i], gy))
+            else:
+                add(i, maxpool_backward(xin, L.ksize, L.stride, gy))
         elif L.kind == SHORTCUT:
             if L.activation == LEAKY:
                 gy = gy * np.where(outs[i] > 0.0, 1.0, net.leaky_slope)

@@ -138,8 +138,6 @@ struct dn_net {
     std::map<GraphKey, GraphPair> graphs;
     std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
-    void *bwd_buf = nullptr;                // library-owned buffer of the input-gradient pass
-    size_t bwd_bytes = 0;
     std::mutex mu;
 };
 
@@ -638,7 +636,6 @@ extern "C" void dn_net_destroy(dn_net *net)
     for (auto &kv : net->host_vals)
         for (unsigned char *b : kv.second) (void)hipHostFree(b);
     if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
-    if (net->bwd_buf) (void)hipFree(net->bwd_buf);
     delete net;
 }
 
@@ -1798,7 +1795,7 @@ static dn_status enqueue_input_gradient(const dn_net *net, const BwdPlan &b, cha
     return DN_OK;
 }
 
-static dn_status bwd_prepare(dn_net *net, int layer, int batch, int h, int w, BwdPlan *b, size_t extra = 0)
+static dn_status bwd_prepare(const dn_net *net, int layer, int batch, int h, int w, BwdPlan *b)
 {
     if (net->o.dtype != DN_F32 && net->o.dtype != DN_BF16)
         return fail(DN_EUNSUPPORTED, "input gradient: F32 and BF16 nets only");
@@ -1806,24 +1803,30 @@ static dn_status bwd_prepare(dn_net *net, int layer, int batch, int h, int w, Bw
     STCHK(check_dims(net, batch, h, w));
     for (size_t i = 0; i < net->L.size(); ++i)
         if (net->L[i].kind == DN_CONV && !net->cw[i].wb) return fail(DN_ESTATE, "conv layer %zu has no backward weights", i);
-    STCHK(make_bwd_plan(net, layer, batch, h, w, b));
-    const size_t need = b->total + extra;
-    std::lock_guard<std::mutex> g(net->mu);
-    if (net->bwd_bytes < need) {
-        if (net->bwd_buf) {
-            HIPCHK(hipDeviceSynchronize());
-            HIPCHK(hipFree(net->bwd_buf));
-            net->bwd_buf = nullptr;
-            net->bwd_bytes = 0;
-        }
-        HIPCHK(hipMalloc(&net->bwd_buf, need));
-        net->bwd_bytes = need;
-    }
+    return make_bwd_plan(net, layer, batch, h, w, b);
+}
+
+extern "C" dn_status dn_input_gradient_arena_bytes(const dn_net *net, int layer, int batch, int h, int w, size_t *bytes)
+{
+    if (!net || !bytes) return fail(DN_EINVAL, "NULL argument");
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
+    *bytes = b.total;
     return DN_OK;
 }
 
-extern "C" dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
-                                       void *stream)
+static dn_status bwd_arena_check(const BwdPlan &b, const void *arena, size_t arena_bytes)
+{
+    if (!arena) return fail(DN_ESTATE, "input gradient: no arena (bind one or pass one)");
+    if ((uintptr_t)arena & 255) return fail(DN_EINVAL, "input gradient: arena must be 256-byte aligned");
+    if (arena_bytes < b.total)
+        return fail(DN_ENOMEM, "input gradient: arena has %zu bytes, the pass needs %zu (dn_input_gradient_arena_bytes)",
+                    arena_bytes, b.total);
+    return DN_OK;
+}
+
+static dn_status input_gradient_on(dn_net *net, void *arena, size_t arena_bytes, int layer, const float *x, int batch,
+                                   int h, int w, float *grad, hipStream_t s)
 {
     if (!net) return fail(DN_EINVAL, "net is NULL");
     if (!grad) return fail(DN_EINVAL, "grad is NULL");
@@ -1831,16 +1834,74 @@ extern "C" dn_status dn_input_gradient(dn_net *net, int layer, const float *x, i
     HIPCHK(hipSetDevice(net->o.device));
     BwdPlan b;
     STCHK(bwd_prepare(net, layer, batch, h, w, &b));
-    hipStream_t s = (hipStream_t)stream;
-    char *base = (char *)net->bwd_buf;
+    STCHK(bwd_arena_check(b, arena, arena_bytes));
+    char *base = (char *)arena;
     STCHK(enqueue_input_gradient(net, b, base, x, s));
     HIPCHK(hipMemcpyAsync(grad, base + b.gin_off, (size_t)batch * net->o.in_c * h * w * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
     return DN_OK;
 }
 
-extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, int h, int w, float rate, int iters,
-                                  void *stream)
+extern "C" dn_status dn_input_gradient(dn_net *net, int layer, const float *x, int batch, int h, int w, float *grad,
+                                       void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    return input_gradient_on(net, net->arena, net->arena_bytes, layer, x, batch, h, w, grad, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_input_gradient_arena(dn_net *net, void *arena, size_t arena_bytes, int layer, const float *x,
+                                             int batch, int h, int w, float *grad, void *stream)
+{
+    return input_gradient_on(net, arena, arena_bytes, layer, x, batch, h, w, grad, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_input_gradient_readback(const dn_net *net, void *arena, size_t arena_bytes, int layer,
+                                                int batch, int h, int w, int of_layer, int what, void *out,
+                                                size_t out_bytes, int *available, void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    if (what < 0 || what > 2) return fail(DN_EINVAL, "readback: unknown kind %d", what);
+    HIPCHK(hipSetDevice(net->o.device));
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
+    STCHK(bwd_arena_check(b, arena, arena_bytes));
+    if (of_layer < 0 || of_layer > layer) return fail(DN_EINVAL, "readback: layer %d outside 0..%d", of_layer, layer);
+    const Plan &p = b.p;
+    const int v = of_layer + 1;
+    const Value &vv = p.vals[v];
+    bool have = false;
+    size_t need = 0;
+    const Op *fused = nullptr;  // the conv op whose fused pool is layer of_layer
+    for (int k = 0; k < b.nops; ++k) {
+        if (p.ops[k].out == v) have = true;
+        if (p.ops[k].kind == OP_CONV && p.ops[k].pool && p.ops[k].layer == of_layer) fused = &p.ops[k];
+    }
+    if (what == 1) {
+        have = fused != nullptr;
+        need = fused ? (size_t)batch * fused->Ho * fused->Wo * fused->cout_p : 0;
+    } else if (what == 2) {
+        have = true;  // every value 0..seed has a gradient buffer
+        need = (size_t)batch * vv.c * vv.h * vv.w * sizeof(float);
+    } else {
+        need = (size_t)batch * vv.c * vv.h * vv.w * sizeof(float);
+    }
+    if (available) *available = have ? 1 : 0;
+    if (!out) return DN_OK;
+    if (!have) return fail(DN_EINVAL, "readback: the pass stores no %s for layer %d",
+                           what == 1 ? "argmax codes" : "output", of_layer);
+    if (out_bytes < need) return fail(DN_EINVAL, "readback: output buffer has %zu bytes, needs %zu", out_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)arena;
+    if (what == 1)
+        HIPCHK(hipMemcpyAsync(out, base + fused->argmax_off, need, hipMemcpyDeviceToDevice, s));
+    else
+        HIPCHK(launch_egress(p.dtype, base + (what == 0 ? vv.off : b.goff[v]), batch, vv.c, vv.h, vv.w, vv.cp, 1.0f,
+                             (float *)out, s));
+    return DN_OK;
+}
+
+static dn_status nightmare_on(dn_net *net, void *arena, size_t arena_bytes, int layer, float *x, int batch, int h,
+                              int w, float rate, int iters, hipStream_t s)
 {
     if (!net) return fail(DN_EINVAL, "net is NULL");
     if (iters < 0) return fail(DN_EINVAL, "iters must be >= 0");
@@ -1849,14 +1910,27 @@ extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, i
     HIPCHK(hipSetDevice(net->o.device));
     BwdPlan b;
     STCHK(bwd_prepare(net, layer, batch, h, w, &b));
-    hipStream_t s = (hipStream_t)stream;
-    char *base = (char *)net->bwd_buf;
+    STCHK(bwd_arena_check(b, arena, arena_bytes));
+    char *base = (char *)arena;
     for (int it = 0; it < iters; ++it) {
         STCHK(enqueue_input_gradient(net, b, base, x, s));
         HIPCHK(launch_ascend(x, (const float *)(base + b.gin_off), (double *)(base + b.mabs_off), batch,
                              (size_t)net->o.in_c * h * w, rate, s));
     }
     return DN_OK;
+}
+
+extern "C" dn_status dn_nightmare(dn_net *net, int layer, float *x, int batch, int h, int w, float rate, int iters,
+                                  void *stream)
+{
+    if (!net) return fail(DN_EINVAL, "net is NULL");
+    return nightmare_on(net, net->arena, net->arena_bytes, layer, x, batch, h, w, rate, iters, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_nightmare_arena(dn_net *net, void *arena, size_t arena_bytes, int layer, float *x, int batch,
+                                        int h, int w, float rate, int iters, void *stream)
+{
+    return nightmare_on(net, arena, arena_bytes, layer, x, batch, h, w, rate, iters, (hipStream_t)stream);
 }
 
 // Time `launch` (which enqueues one candidate) 1 + 5 times; the mean of the last 5 in ms, or a status.
@@ -1879,11 +1953,10 @@ template <typename F> static dn_status time_candidate(F launch, hipEvent_t e0, h
 constexpr size_t BWD_TUNE_SCRATCH = (size_t)512 << 20;
 
 static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int w, hipStream_t s, hipEvent_t e0,
-                                   hipEvent_t e1)
+                                   hipEvent_t e1, char *base)
 {
     BwdPlan b;
-    STCHK(bwd_prepare(net, layer, batch, h, w, &b, BWD_TUNE_SCRATCH));
-    char *base = (char *)net->bwd_buf;
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
     char *scratch = base + b.total;  // candidate split-K partials (and spread gradients) go here
     Plan p = b.p;
     p.ws_off = b.total;
@@ -1971,12 +2044,20 @@ extern "C" dn_status dn_autotune_backward(dn_net *net, int layer, int batch, int
     if (!net) return fail(DN_EINVAL, "net is NULL");
     HIPCHK(hipSetDevice(net->o.device));
     load_tune_cache(net);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    const dn_status rc = autotune_backward(net, layer, batch, h, w, (hipStream_t)stream, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    BwdPlan b;
+    STCHK(bwd_prepare(net, layer, batch, h, w, &b));
+    // a synchronous tuning call: the pass's buffers and the candidates'
+    // scratch live in a temporary allocation freed before returning
+    char *base = nullptr;
+    HIPCHK(hipMalloc(&base, b.total + BWD_TUNE_SCRATCH));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    dn_status rc = DN_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(DN_EHIP, "hipEventCreate");
+    if (rc == DN_OK) rc = autotune_backward(net, layer, batch, h, w, (hipStream_t)stream, e0, e1, base);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(base);
     if (rc == DN_OK) {
         std::lock_guard<std::mutex> g(net->mu);
         save_tune_cache(net);

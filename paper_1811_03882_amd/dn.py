@@ -99,8 +99,12 @@ SIGNATURES = {
     "dn_conv_backward_data": (_i, [ctypes.POINTER(ConvDesc), _vp, _vp, _vp, _vp, _i, _vp, _vp, _sz, _vp]),
     "dn_maxpool_backward": (_i, [ctypes.POINTER(PoolDesc), _vp, _vp, _i, _vp, _vp]),
     "dn_leaky_backward": (_i, [_i, _sz, _vp, _vp, _f, _vp, _vp]),
+    "dn_input_gradient_arena_bytes": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "dn_input_gradient": (_i, [_vp, _i, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_input_gradient_arena": (_i, [_vp, _vp, _sz, _i, _vp, _i, _i, _i, _vp, _vp]),
+    "dn_input_gradient_readback": (_i, [_vp, _vp, _sz, _i, _i, _i, _i, _i, _i, _vp, _sz, _ip, _vp]),
     "dn_nightmare": (_i, [_vp, _i, _vp, _i, _i, _i, _f, _i, _vp]),
+    "dn_nightmare_arena": (_i, [_vp, _vp, _sz, _i, _vp, _i, _i, _i, _f, _i, _vp]),
     "dn_autotune_backward": (_i, [_vp, _i, _i, _i, _i, _vp]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
@@ -303,14 +307,39 @@ class Net:
         check(LIB.dn_time_layer(self._h, layer, batch, h, w, iters, stream_handle(stream), ctypes.byref(ms)))
         return ms.value
 
+    def input_gradient_arena_bytes(self, layer: int, batch: int, h: int, w: int) -> int:
+        n = _sz()
+        check(LIB.dn_input_gradient_arena_bytes(self._h, layer, batch, h, w, ctypes.byref(n)))
+        return n.value
+
     def input_gradient(self, layer: int, x, batch: int, h: int, w: int, grad, stream=None) -> None:
         check(LIB.dn_input_gradient(self._h, layer, ptr(x), batch, h, w, ptr(grad), stream_handle(stream)))
+
+    def input_gradient_arena(self, arena, nbytes: int, layer: int, x, batch: int, h: int, w: int, grad,
+                             stream=None) -> None:
+        check(LIB.dn_input_gradient_arena(self._h, ptr(arena), nbytes, layer, ptr(x), batch, h, w, ptr(grad),
+                                          stream_handle(stream)))
 
     def autotune_backward(self, layer: int, batch: int, h: int, w: int, stream=None) -> None:
         check(LIB.dn_autotune_backward(self._h, layer, batch, h, w, stream_handle(stream)))
 
+    def input_gradient_readback(self, arena, nbytes: int, layer: int, batch: int, h: int, w: int, of_layer: int,
+                                what: int, out=None, out_bytes: int = 0, stream=None) -> bool:
+        """Copy a buffer of the last input-gradient pass on `arena` into `out`
+        (what: 0 stored output, 1 fused-pool argmax codes, 2 gradient); returns
+        whether the pass keeps that buffer."""
+        av = _i()
+        check(LIB.dn_input_gradient_readback(self._h, ptr(arena), nbytes, layer, batch, h, w, of_layer, what,
+                                             ptr(out), out_bytes, ctypes.byref(av), stream_handle(stream)))
+        return bool(av.value)
+
     def nightmare(self, layer: int, x, batch: int, h: int, w: int, rate: float, iters: int, stream=None) -> None:
         check(LIB.dn_nightmare(self._h, layer, ptr(x), batch, h, w, rate, iters, stream_handle(stream)))
+
+    def nightmare_arena(self, arena, nbytes: int, layer: int, x, batch: int, h: int, w: int, rate: float,
+                        iters: int, stream=None) -> None:
+        check(LIB.dn_nightmare_arena(self._h, ptr(arena), nbytes, layer, ptr(x), batch, h, w, rate, iters,
+                                     stream_handle(stream)))
 
     def layer_plan(self, layer: int, batch: int, h: int, w: int):
         v = [_i() for _ in range(4)]

@@ -5,30 +5,21 @@ L2 on the same inputs); the max-pool gradient and the leaky gradient bit-exact
 on inputs whose results are representable (ties included, so the
 first-maximum rule is exercised).
 
-Whole-pass parity: dn_input_gradient and dn_nightmare against the oracle.
-F32 against the plain FP64 gradient (1e-5).  BF16 against the gradient of
-the BF16 path's definition (image, folded weights and activations stored in
-BF16, oracle.backward.input_gradient_stored), whose leaky and max-pool
-branches are taken on stored BF16 values as on the device.  Those branches
-are discontinuities: two correct BF16 evaluations whose stored activations
-differ by one unit in the last place in a few elements (FP32 versus FP64
-accumulation crossing a rounding boundary) take a few different branches,
-and in a deep residual stack that moves the gradient by more than 2e-2.  The
-BF16 gate is therefore max(2e-2, 2 s), where s is the oracle's own change
-when 0.1% of the image's pixels move by one BF16 unit (computed on the host
-from the oracle alone).  The same mechanism reaches F32 at the full 416x416
-size: a branch variable within the FP32 forward's error (about 1e-6
-relative) of its threshold occurs about once per million branch variables,
-an image carries about 4.4 million of them, and each different branch moves
-about one element's share of the gradient, so a few flips give a relative
-L2 change of order sqrt(flips / 2.8e6) ~ 1e-3; the full-size F32 gate is 1e-2
-(about 70 flips), the small-size F32 gate stays 1e-5 (0.06 flips expected)."""
+Whole-pass parity (dn_input_gradient_arena, dn_nightmare_arena): the pass's
+branch decisions (leaky signs, pooling window choices) are read back from the
+arena; every decision that differs from the FP64 oracle's own must lie within
+the forward's error bound of its threshold (the count per image is printed),
+and the gradient must match the oracle's gradient on the device's piece at the
+stated gates, FP32 1e-5 and BF16 2e-2 relative L2 per image, at every size
+including the full 64 x 416 x 416 batch (tests/branch_check.py)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
 from oracle import backward as ob
+from oracle import net as onet
+from tests import branch_check as BC
 from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
@@ -194,36 +185,6 @@ def _small_net():
     ])
 
 
-def _gpu_gradient(dn, net, dtype, x, layer, seed):
-    torch = G.torch_cuda()
-    n, _, h, w = x.shape
-    gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype, leaky_slope=net.leaky_slope, bn_eps=net.bn_eps)
-    gn.load_params(synth.make_params(net, seed))
-    xd = G.dev(x.astype(np.float32))
-    g = torch.empty_like(xd)
-    gn.input_gradient(layer, xd, n, h, w, g)
-    torch.cuda.synchronize()
-    return gn, g.cpu().numpy().astype(np.float64)
-
-
-def _ref_gradient(net, dtype, params, x, layer):
-    if dtype == 0:
-        return ob.input_gradient(net, params, x, layer)
-    return ob.input_gradient_stored(net, params, x, layer)
-
-
-def _gate(net, dtype, params, x, layer, ref, full_size=False):
-    """F32: 1e-5, or 1e-2 at the full 416x416 size (see the module notes).
-    BF16: max(2e-2, twice the BF16 definition's own change when 0.1% of the
-    pixels move by one BF16 unit)."""
-    if dtype == 0:
-        return 1e-2 if full_size else G.GATE[0]
-    rng = np.random.default_rng([layer, 99])
-    xp = x * np.where(rng.random(x.shape) < 1e-3, 1 + 2.0 ** -8, 1.0)
-    s = G.rel_l2(ob.input_gradient_stored(net, params, xp, layer), ref)
-    return max(G.GATE[1], 2 * s)
-
-
 def _ingest_net():
     # a 5x5 stem cannot take the first-layer kernel: the image goes through the
     # ingest kernel, and the stem's backward-data conv has pad 4 - 2 = 2
@@ -252,34 +213,19 @@ def test_input_gradient_parity(dn, dtype, case):
     params = synth.make_params(net, seed)
     x = synth.make_input(net, n, seed, h=h, w=w)
     for layer in layers:
-        _, got = _gpu_gradient(dn, net, dtype, x, layer, seed)
-        ref = _ref_gradient(net, dtype, params, x, layer)
-        err, gate = G.rel_l2(got, ref), _gate(net, dtype, params, x, layer, ref)
-        print("input gradient %s %s layer %d rel_l2=%.3e gate %.3e" % (G.NAME[dtype], net.name, layer, err, gate))
-        assert err < gate
+        print("case %s %s layer %d" % (net.name, G.NAME[dtype], layer), flush=True)
+        BC.check_pass(dn, net, dtype, params, x, layer)
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
 def test_input_gradient_after_backward_autotune(dn, dtype):
     """Tuned tiles (split-K, accumulating epilogues, halo) for every conv of
     the pass, forward and backward, give the same gradient within the gates."""
-    torch = G.torch_cuda()
     net = synth.residual52(units=(1, 2), widths=(64, 128), in_hw=32)
     n, h, w, seed, layer = 2, 32, 32, 37, 11
     params = synth.make_params(net, seed)
     x = synth.make_input(net, n, seed, h=h, w=w)
-    gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype)
-    gn.load_params(params)
-    gn.autotune_backward(layer, n, h, w)
-    xd = G.dev(x.astype(np.float32))
-    g = torch.empty_like(xd)
-    gn.input_gradient(layer, xd, n, h, w, g)
-    torch.cuda.synchronize()
-    got = g.cpu().numpy().astype(np.float64)
-    ref = _ref_gradient(net, dtype, params, x, layer)
-    err, gate = G.rel_l2(got, ref), _gate(net, dtype, params, x, layer, ref)
-    print("tuned input gradient %s rel_l2=%.3e gate %.3e" % (G.NAME[dtype], err, gate))
-    assert err < gate
+    BC.check_pass(dn, net, dtype, params, x, layer, tune=True, label="tuned residual_32")
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
@@ -288,23 +234,22 @@ def test_nightmare_step_parity(dn, dtype):
     net = _small_net()
     n, h, w, seed, layer, rate = 2, 24, 20, 34, 5, 0.02
     params = synth.make_params(net, seed)
-    x = synth.make_input(net, n, seed, h=h, w=w)
+    x32 = synth.make_input(net, n, seed, h=h, w=w).astype(np.float32).astype(np.float64)
+    got, stored, codes = BC.run_device_pass(dn, net, dtype, params, x32, layer, nightmare_rate=rate)
+    ref_outs = onet.forward(net, params, x32, upto=layer + 1)
+    passes, picks, flips, _ = BC.check_decisions(net, dtype, x32, layer, stored, codes, ref_outs)
+    want = ob.ascent_step(x32, ob.input_gradient_on_piece(net, params, x32, layer, passes, picks), rate)
+    # the step itself (x' - x) carries the whole error; compare it, clipped as on both sides
+    err = G.rel_l2(got - x32, want - x32)
+    print("nightmare step %s rel_l2=%.3e, branch flips per image %s" % (G.NAME[dtype], err, list(flips)))
+    assert err < G.GATE[dtype]
+    assert got.min() >= 0.0 and got.max() <= 1.0
+    # further iterations (bound arena) keep the image in range and move it up the energy
     gn = dn.Net(net.layers, net.in_c, h, w, n, dtype=dtype, leaky_slope=net.leaky_slope, bn_eps=net.bn_eps)
     gn.load_params(params)
-    xd = G.dev(x.astype(np.float32))
-    gn.nightmare(layer, xd, n, h, w, rate, 1)
-    torch.cuda.synchronize()
-    got = xd.cpu().numpy().astype(np.float64)
-    x32 = x.astype(np.float32).astype(np.float64)
-    ref = _ref_gradient(net, dtype, params, x32, layer)
-    want = ob.ascent_step(x32, ref, rate)
-    # the step itself (x' - x) carries the whole error; compare it, clipped as on both sides
-    err, gate = G.rel_l2(got - x32, want - x32), _gate(net, dtype, params, x32, layer, ref)
-    print("nightmare step %s rel_l2=%.3e gate %.3e" % (G.NAME[dtype], err, gate))
-    assert err < gate
-    assert got.min() >= 0.0 and got.max() <= 1.0
-    # further iterations keep the image in range and move it up the energy
+    gn.bind_arena(G.empty_bytes(gn.input_gradient_arena_bytes(layer, n, h, w)))
     e0 = ob.energy(net, params, got, layer)
+    xd = G.dev(got.astype(np.float32))
     gn.nightmare(layer, xd, n, h, w, rate, 3)
     torch.cuda.synchronize()
     x4 = xd.cpu().numpy().astype(np.float64)
@@ -313,21 +258,17 @@ def test_nightmare_step_parity(dn, dtype):
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
-def test_input_gradient_plain9_full_size_sampled(dn, dtype):
+def test_input_gradient_plain9_full_size_all_images(dn, dtype):
     """The 9-layer net at its full size (batch 64, 416x416), gradient of the
-    last layer's energy: sampled images against the oracle, each image
-    computed one by one on the host."""
+    last layer's energy: every image against the oracle on the device's piece,
+    with every differing branch decision checked against the forward-error
+    bound."""
     net = synth.plain9()
-    n, h, w, seed, layer = 64, 416, 416, 35, 14
+    n, seed, layer = 64, 35, 14
     params = synth.make_params(net, seed)
     x = synth.make_input(net, n, seed)
-    _, got = _gpu_gradient(dn, net, dtype, x, layer, seed)
+    errs, got, _, _ = BC.check_pass(dn, net, dtype, params, x, layer, label="plain9 b64 416")
     assert np.all(np.isfinite(got))
-    for i in (0, 63):
-        ref = _ref_gradient(net, dtype, params, x[i:i + 1], layer)
-        err, gate = G.rel_l2(got[i:i + 1], ref), _gate(net, dtype, params, x[i:i + 1], layer, ref, full_size=True)
-        print("plain9 b64 %s image %d rel_l2=%.3e gate %.3e" % (G.NAME[dtype], i, err, gate))
-        assert err < gate
 
 
 def test_input_gradient_errors(dn):
@@ -343,6 +284,14 @@ def test_input_gradient_errors(dn):
     with pytest.raises(dn.DnError) as e:
         gn.input_gradient(8, x, 1, 24, 20, g)
     assert e.value.status == dn.DN_EINVAL  # no such layer
+    with pytest.raises(dn.DnError) as e:
+        gn.input_gradient(7, x, 1, 24, 20, g)
+    assert e.value.status == dn.DN_ESTATE  # no arena bound
+    need = gn.input_gradient_arena_bytes(7, 1, 24, 20)
+    small = G.empty_bytes(need // 2)
+    with pytest.raises(dn.DnError) as e:
+        gn.input_gradient_arena(small, need // 2, 7, x, 1, 24, 20, g)
+    assert e.value.status == dn.DN_ENOMEM
     f8 = dn.Net(net.layers, 3, 24, 20, 1, dtype=dn.FP8)
     f8.load_params(synth.make_params(net, 0))
     with pytest.raises(dn.DnError) as e:

@@ -204,15 +204,130 @@ def test_round_bf16_hand_values():
     assert ob.round_bf16(np.array([one + 2.0 ** -7]))[0] == one + 2.0 ** -7  # representable: unchanged
 
 
-@pytest.mark.parametrize("layer", [2, 7])
-def test_stored_gradient_without_rounding_is_the_plain_gradient(layer):
+def _first_max_pick(x, size, stride):
+    """Window decisions of a max pool by the first-maximum rule (row-major
+    window order, taps outside the input never win), by brute force."""
+    n, c, h, w = x.shape
+    ho, wo, off = (h - 1) // stride + 1, (w - 1) // stride + 1, (size - 1) // 2
+    pick = np.empty((n, c, ho, wo), np.int64)
+    for a in range(n):
+        for k in range(c):
+            for i in range(ho):
+                for j in range(wo):
+                    best, arg = -np.inf, -1
+                    for u in range(size):
+                        for v in range(size):
+                            yy, xx = i * stride - off + u, j * stride - off + v
+                            if 0 <= yy < h and 0 <= xx < w and x[a, k, yy, xx] > best:
+                                best, arg = x[a, k, yy, xx], u * size + v
+                    pick[a, k, i, j] = arg
+    return pick
+
+
+def _own_decisions(net, params, x, layer):
+    from oracle import net as onet
+    outs = onet.forward(net, params, x, upto=layer + 1)
+    ins = [x] + outs[:-1]
+    passes, picks = {}, {}
+    for i in range(layer + 1):
+        L = net.layers[i]
+        if L.kind == synth.CONV and L.activation == synth.LEAKY:
+            passes[i] = outs[i] > 0.0  # a leaky output has its pre-activation's sign
+        elif L.kind == synth.MAXPOOL:
+            picks[i] = _first_max_pick(ins[i], L.ksize, L.stride)
+    return passes, picks
+
+
+@pytest.mark.parametrize("layer", [2, 5, 7])
+def test_gradient_on_the_oracles_own_piece_is_the_plain_gradient(layer):
     net = _small_net()
     params = synth.make_params(net, 22)
     x = synth.make_input(net, 2, 22)
     plain = ob.input_gradient(net, params, x, layer)
-    ident = lambda a: np.asarray(a, np.float64)
-    same = ob.input_gradient_stored(net, params, x, layer, q=ident, qb=ident)
-    np.testing.assert_allclose(same, plain, rtol=1e-10, atol=1e-12 * np.abs(plain).max())
-    bf = ob.input_gradient_stored(net, params, x, layer)
-    err = np.linalg.norm(bf - plain) / np.linalg.norm(plain)
-    assert 0 < err < 0.5  # rounding changes it, but it stays the same gradient
+    passes, picks = _own_decisions(net, params, x, layer)
+    got = ob.input_gradient_on_piece(net, params, x, layer, passes, picks)
+    np.testing.assert_allclose(got, plain, rtol=1e-12, atol=1e-13 * np.abs(plain).max())
+
+
+def _brute_piece_gradient(x, p1, p2, eps, slope, passes, pick):
+    """Pure-Python loops on a 1-image net: conv3x3 pad 1 + bias + BN + leaky
+    (decisions `passes`), 2x2 stride-1 max pool (decisions `pick`), conv1x1 +
+    bias; gradient of 1/2 * sum(out^2) with respect to x on that piece."""
+    _, C, H, W = x.shape
+    K = p1.w.shape[0]
+    K2 = p2.w.shape[0]
+    sc = [p1.gamma[k] / np.sqrt(p1.var[k] + eps) for k in range(K)]
+    a1 = [[[0.0] * W for _ in range(H)] for _ in range(K)]
+    for k in range(K):
+        for i in range(H):
+            for j in range(W):
+                z = 0.0
+                for c in range(C):
+                    for r in range(3):
+                        for t in range(3):
+                            yy, xx = i - 1 + r, j - 1 + t
+                            if 0 <= yy < H and 0 <= xx < W:
+                                z += p1.w[k, c, r, t] * x[0, c, yy, xx]
+                z = (z + p1.bias[k] - p1.mean[k]) * sc[k] + p1.beta[k]
+                a1[k][i][j] = z if z > 0 else slope * z
+    y = [[[max(a1[k][i + u][j + v] for u in range(2) for v in range(2) if i + u < H and j + v < W)
+           for j in range(W)] for i in range(H)] for k in range(K)]
+    out = [[[sum(p2.w[m, k, 0, 0] * y[k][i][j] for k in range(K)) + p2.bias[m] for j in range(W)]
+            for i in range(H)] for m in range(K2)]
+    gy = [[[sum(p2.w[m, k, 0, 0] * out[m][i][j] for m in range(K2)) for j in range(W)] for i in range(H)]
+          for k in range(K)]
+    ga = [[[0.0] * W for _ in range(H)] for _ in range(K)]
+    for k in range(K):
+        for i in range(H):
+            for j in range(W):
+                u, v = divmod(int(pick[0, k, i, j]), 2)
+                ga[k][i + u][j + v] += gy[k][i][j]
+    gx = np.zeros(x.shape)
+    for k in range(K):
+        for i in range(H):
+            for j in range(W):
+                gz = ga[k][i][j] * (1.0 if passes[0, k, i, j] else slope) * sc[k]
+                for c in range(C):
+                    for r in range(3):
+                        for t in range(3):
+                            yy, xx = i - 1 + r, j - 1 + t
+                            if 0 <= yy < H and 0 <= xx < W:
+                                gx[0, c, yy, xx] += gz * p1.w[k, c, r, t]
+    return gx
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gradient_on_a_given_piece_matches_brute_force(seed):
+    net = synth.Net("piece", 2, 5, 4, [synth.conv(3, 3), synth.maxpool(2, 1),
+                                        synth.conv(2, 1, bn=False, act=synth.LINEAR)])
+    params = synth.make_params(net, 60 + seed)
+    x = synth.make_input(net, 1, 60 + seed)
+    passes, picks = _own_decisions(net, params, x, 2)
+    rng = np.random.default_rng([61, seed])
+    # flip a third of the leaky decisions and re-pick a third of the windows
+    # (any tap inside the input): a piece the oracle would not take itself
+    flip = rng.random(passes[0].shape) < 1 / 3
+    passes[0] = np.where(flip, ~passes[0], passes[0])
+    pick = picks[1].copy()
+    H, W = 5, 4
+    for idx in zip(*np.nonzero(rng.random(pick.shape) < 1 / 3)):
+        _, _, i, j = idx
+        valid = [u * 2 + v for u in range(2) for v in range(2) if i + u < H and j + v < W]
+        pick[idx] = valid[rng.integers(len(valid))]
+    picks[1] = pick
+    got = ob.input_gradient_on_piece(net, params, x, 2, passes, picks)
+    want = _brute_piece_gradient(x, params[0], params[2], net.bn_eps, net.leaky_slope, passes[0], picks[1])
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-13 * np.abs(want).max())
+    # the piece matters: the oracle's own piece gives another gradient
+    assert np.abs(ob.input_gradient(net, params, x, 2) - got).max() > 1e-6 * np.abs(got).max()
+
+
+def test_picked_pool_gradient_rejects_taps_outside_the_input():
+    dy = np.ones((1, 1, 2, 2))
+    pick = np.zeros((1, 1, 2, 2), np.int64)
+    pick[0, 0, 1, 1] = 3  # window at the bottom-right corner of a 2x2 input, stride 1: tap (2, 2) is outside
+    with pytest.raises(ValueError):
+        ob.maxpool_backward_picked((1, 1, 2, 2), 2, 1, pick, dy)
+    pick[0, 0, 1, 1] = 0
+    got = ob.maxpool_backward_picked((1, 1, 2, 2), 2, 1, pick, dy)
+    np.testing.assert_array_equal(got[0, 0], [[1.0, 1.0], [1.0, 1.0]])
