@@ -48,7 +48,8 @@ typedef enum dn_status {
     DN_ENOMEM = -2,        /* allocation failed or arena too small */
     DN_EHIP = -3,          /* a HIP runtime call failed */
     DN_ESTATE = -4,        /* call out of order (e.g. forward before load/bind) */
-    DN_EUNSUPPORTED = -5   /* valid request the library does not implement */
+    DN_EUNSUPPORTED = -5,  /* valid request the library does not implement */
+    DN_ETIMEDOUT = -6      /* a placed forward ran past its time limit */
 } dn_status;
 
 typedef enum dn_dtype { DN_F32 = 0, DN_BF16 = 1, DN_FP8_E4M3 = 2 } dn_dtype;
@@ -374,6 +375,108 @@ dn_status dn_detect(const float *y, int batch, int anchors, int classes, int h, 
                     const float *anchor_wh, float thresh, float nms_thresh, int max_det,
                     void *workspace, size_t ws_bytes, float *dets, int *det_index, int *counts,
                     void *stream);
+
+/* ---- placement of layers between the host CPU and the GPU: the paper's
+ * offload search (Sec. 3.3 and Sec. 4) with its transfer rule (Sec. 3.2)
+ * and GA parameters (Sec. 5.1.2), applied to this library's layers.  A gene
+ * holds one byte per layer of the net (gene_len = number of layers):
+ * 1 = the layer runs on the GPU (the library's kernels), 0 = on the host CPU
+ * (the library's host FP32 layer code, worker threads: $DN_CPU_THREADS, else
+ * $OMP_NUM_THREADS, else up to 16).  The host side runs only where a gene
+ * puts it; dn_forward never uses it.  FP32 resident-mode nets only (else
+ * DN_EUNSUPPORTED).
+ *
+ * Transfers follow Sec. 3.2 at layer granularity: weights stay where they
+ * were defined (device weights for GPU layers; a host copy of the same folded
+ * FP32 weights, read back once on the first placed call, for host layers); a
+ * layer output crosses once, right after the layer that produces it, when a
+ * layer on the other side reads it; the image crosses once when a GPU layer
+ * reads it; the result crosses once when a GPU layer produces it.  A conv and
+ * the 2x2/2 pool (or linear shortcut) after it run fused when both are on
+ * the GPU, as in the resident forward, so the all-GPU gene runs the resident
+ * plan with one input and one output crossing. */
+
+/* Device bytes a placed forward of (batch, h, w) needs in the bound arena,
+ * for any gene (every layer output keeps its own buffer, plus split-K
+ * scratch and FP32 staging of the image and the result). */
+dn_status dn_placed_arena_bytes(const dn_net *net, int batch, int h, int w, size_t *bytes);
+
+/* The crossings a gene implies (host logic, nothing runs): h2d / d2h counts
+ * and bytes of copies per forward, image and result included.  Any output
+ * pointer may be NULL.  gene_len must equal the number of layers and every
+ * gene value be 0 or 1 (else DN_EINVAL). */
+dn_status dn_placed_transfers(const dn_net *net, const unsigned char *gene, int gene_len, int batch, int h, int w,
+                              int *h2d, int *d2h, size_t *h2d_bytes, size_t *d2h_bytes);
+
+/* Forward with each layer on the side its gene value names.  x, y: host
+ * NCHW FP32 (x [batch][in_c][h][w], y of dn_net_output_shape).  Uses the
+ * bound arena (at least dn_placed_arena_bytes, else DN_ENOMEM) and, per
+ * (batch, h, w), pinned host buffers the library allocates on first use and
+ * keeps until destroy.  Synchronous: returns after y is written.  With
+ * timeout_s > 0 a forward still running after timeout_s seconds stops
+ * between two layers and returns DN_ETIMEDOUT (y is then undefined). */
+dn_status dn_forward_placed(dn_net *net, const unsigned char *gene, int gene_len, const float *x, int batch, int h,
+                            int w, float *y, double timeout_s, void *stream);
+
+/* Host FP32 layer code of the placement on host buffers (checked on their
+ * own by the tests): dn_cpu_conv2d runs the conv of d (dtype DN_F32, no
+ * fused pool or residual, input_nchw = 0, else DN_EUNSUPPORTED) with
+ * already folded host weights w [cout][in_c][k][k] and bias [cout]: y =
+ * act(conv(x, w) + bias), x / y NHWC with padded channels
+ * (dn_channel_pad(DN_F32, .)); dn_cpu_maxpool pools NHWC x into y like
+ * dn_maxpool (dtype DN_F32). */
+dn_status dn_cpu_conv2d(const dn_conv_desc *d, const float *x, const float *w, const float *bias, float *y);
+dn_status dn_cpu_maxpool(const dn_pool_desc *d, const float *x, float *y);
+
+typedef struct dn_ga_params {
+    int population;          /* M, >= 1 (paper: 30) */
+    int generations;         /* T, >= 1 (paper: 20) */
+    double crossover;        /* Pc in [0, 1] (paper: 0.9), one-point */
+    double mutation;         /* Pm in [0, 1] (paper: 0.05), per gene value */
+    double timeout_s;        /* > 0: a slower (or failed) measurement scores penalty_s */
+    double penalty_s;        /* > 0 (paper: 1000 s for its 3-minute limit) */
+    unsigned long long seed; /* SplitMix64 state the search starts from */
+} dn_ga_params;
+
+typedef struct dn_ga_result {
+    double best_seconds;     /* score of best_gene */
+    int evaluations;         /* distinct genes measured */
+    int memo_hits;           /* genes scored from an earlier measurement */
+} dn_ga_result;
+
+/* Measurement callback: seconds taken by the program with this gene; < 0 =
+ * the run failed (scored as penalty_s); NaN aborts the search. */
+typedef double (*dn_ga_measure_fn)(const unsigned char *gene, int gene_len, double timeout_s, void *user);
+
+/* One GA generation step (host logic): from the measured population pop
+ * [M][L] with times seconds [M] to next [M][L], drawing from the SplitMix64
+ * state *rng_state (updated).  Fitness = time^(-1/2); next[0] is the fittest
+ * gene (first on ties) unchanged (elite); the rest are children of pairs
+ * picked by roulette on the fitness, crossed at one random point with
+ * probability Pc, then flipped value by value with probability Pm.  The
+ * draw order per pair is: parent a, parent b, the crossover draw, the cut
+ * point (only when crossing, L >= 2), then one mutation draw per value of
+ * the first child and one per value of the second; the second child of the
+ * last pair is dropped when M - 1 is odd.  seconds must be positive. */
+dn_status dn_ga_next_generation(const dn_ga_params *p, int gene_len, const unsigned char *pop, const double *seconds,
+                                unsigned char *next, unsigned long long *rng_state);
+
+/* T generations of the GA (host logic): initial genes drawn value by value
+ * (top bit of one draw each), each generation measured (a gene seen before
+ * reuses its score), then dn_ga_next_generation.  best_gene [L] receives the
+ * fittest gene measured; gen_best [T] (may be NULL) the best score of each
+ * generation; *res the counts.  DN_EINVAL on bad parameters, DN_ESTATE when
+ * the callback aborted. */
+dn_status dn_ga_search(const dn_ga_params *p, int gene_len, dn_ga_measure_fn measure, void *user,
+                       unsigned char *best_gene, double *gen_best, dn_ga_result *res);
+
+/* The GA over this net's layer placements: each gene is measured as the
+ * median wall time of `reps` dn_forward_placed runs on the host buffers x / y
+ * (after one untimed run of the all-GPU and of the all-CPU gene, which also
+ * allocates the host buffers); timeout_s of p bounds each run.  Same outputs
+ * as dn_ga_search; y holds the last run's result. */
+dn_status dn_ga_place(dn_net *net, const dn_ga_params *p, const float *x, int batch, int h, int w, float *y,
+                      int reps, void *stream, unsigned char *best_gene, double *gen_best, dn_ga_result *res);
 
 /* Measurement helper: the matrix-core throughput the device sustains for the
  * MFMA instruction the convolutions of `dtype` use (16x16x4 FP32, 16x16x32

@@ -3,7 +3,10 @@
     python -m paper_1811_03882_amd.build
 
 Every HIP translation unit is compiled with hipcc for gfx950 only, with packed
-FP32 instructions disabled, and linked into paper_1811_03882_amd/libdn.so.
+FP32 instructions disabled; the host-only units (the host FP32 layer code of
+the layer placement and its genetic search) are compiled with the host C++
+compiler for x86-64-v3 (AVX2 + FMA); all are linked into
+paper_1811_03882_amd/libdn.so.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdn.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["conv.hip", "aux.hip", "backward.hip", "detect.hip", "jacobi.hip", "runtime.cpp"]
+HOST_SOURCES = ["cpu_layers.cpp", "ga.cpp"]
 ARCH = "gfx950"
 
 
@@ -34,9 +38,22 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH,
           "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 
+HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-pthread", "-Wall", "-I", CSRC]
+
+
+def cxx() -> str:
+    for c in (os.environ.get("CXX"), shutil.which("g++"), shutil.which("c++")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("no host C++ compiler found")
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    if src in HOST_SOURCES:
+        cmd = [cxx()] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [hipcc()] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -49,10 +66,11 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source (always; no staleness shortcut) and link libdn.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    srcs = SOURCES + HOST_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

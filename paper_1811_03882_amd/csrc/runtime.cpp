@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -27,7 +28,9 @@
 #include <vector>
 
 #include "../../include/dn.h"
+#include "cpu_layers.h"
 #include "dn_kernels.h"
+#include "ga.h"
 
 using namespace dnk;
 
@@ -81,6 +84,9 @@ struct ConvWeights {
     int kb_pad = 0;
     size_t wbytes = 0;
     bool loaded = false;
+    // placed forward: host copy of the folded FP32 weights in the host conv's
+    // blocked layout (read back from the device on first use)
+    std::vector<float> cpu_w, cpu_b;
 };
 
 enum OpKind { OP_CONV = 0, OP_POOL = 1, OP_ADD = 2 };
@@ -138,6 +144,7 @@ struct dn_net {
     std::map<GraphKey, GraphPair> graphs;
     std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
+    std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_place;  // placed forward
     std::mutex mu;
 };
 
@@ -279,8 +286,12 @@ static bool op_halo_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
 // pool_fuse_upto >= 0 (input-gradient pass, per-layer mode otherwise): fuse a
 // conv with the 2x2/2 pool after it when that pool's layer index is at most
 // pool_fuse_upto; no residual fusion.
+// gene != nullptr (placed forward): layer i runs on the GPU iff gene[i]; a
+// conv fuses with the layer after it only when both are on the GPU, the
+// first-layer kernel is used only when layer 0 is on the GPU, every value
+// keeps its own buffer (no reuse), and the image / result get FP32 staging.
 static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, int h, int w, Plan *out,
-                           int pool_fuse_upto = -1)
+                           int pool_fuse_upto = -1, const unsigned char *gene = nullptr)
 {
     const int n = (int)net->L.size();
     if (batch <= 0 || h <= 0 || w <= 0) return fail(DN_EINVAL, "batch/h/w must be positive (%d, %d, %d)", batch, h, w);
@@ -331,11 +342,12 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         if (d.kind == DN_CONV) {
             op.kind = OP_CONV;
             op.conv = i;
-            op.first = (i == 0) && first_eligible(net, dtype);
+            op.first = (i == 0) && first_eligible(net, dtype) && (!gene || gene[0]);
             op.H = p.vals[i].h; op.W = p.vals[i].w; op.cin_p = p.vals[i].cp;
             op.Ho = p.vals[i + 1].h; op.Wo = p.vals[i + 1].w;
             op.cout = d.cout; op.cout_p = p.vals[i + 1].cp;
-            const bool fuse = mode == DN_MODE_RESIDENT || (pool_fuse_upto >= 0 && i + 1 <= pool_fuse_upto);
+            bool fuse = mode == DN_MODE_RESIDENT || (pool_fuse_upto >= 0 && i + 1 <= pool_fuse_upto);
+            if (gene && (i + 1 >= n || !gene[i] || !gene[i + 1])) fuse = false;
             if (fuse && i + 1 < n && uses[i + 1] == 1) {
                 const dn_layer_desc &nx = net->L[i + 1];
                 if (nx.kind == DN_MAXPOOL && nx.ksize == 2 && nx.stride == 2 && op.Ho % 2 == 0 && op.Wo % 2 == 0) {
@@ -401,10 +413,21 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
             }
         }
     };
-    place(0);
-    for (int k = 0; k < (int)p.ops.size(); ++k) {
-        place(p.ops[k].out);
-        release(k);
+    if (gene) {  // every value its own buffer
+        size_t off = 0;
+        p.vals[0].off = 0;
+        off = p.vals[0].bytes;
+        for (const Op &op : p.ops) {
+            p.vals[op.out].off = off;
+            off += p.vals[op.out].bytes;
+        }
+        top = off;
+    } else {
+        place(0);
+        for (int k = 0; k < (int)p.ops.size(); ++k) {
+            place(p.ops[k].out);
+            release(k);
+        }
     }
     // split-K scratch and tile choice
     size_t ws = 0;
@@ -431,7 +454,7 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
     p.ws_off = align256(top);
     p.ws_bytes = ws;
     size_t end = p.ws_off + ws;
-    if (mode == DN_MODE_PER_LAYER) {
+    if (mode == DN_MODE_PER_LAYER || gene) {
         p.xin_off = align256(end);
         end = p.xin_off + align256((size_t)batch * net->o.in_c * h * w * 4);
         p.yout_off = align256(end);
@@ -633,8 +656,10 @@ extern "C" void dn_net_destroy(dn_net *net)
     (void)hipDeviceSynchronize();
     drop_graphs(net);
     for (auto &cw : net->cw) free_weights(cw);
-    for (auto &kv : net->host_vals)
-        for (unsigned char *b : kv.second) (void)hipHostFree(b);
+    for (auto *m : {&net->host_vals, &net->host_place})
+        for (auto &kv : *m)
+            for (unsigned char *b : kv.second)
+                if (b) (void)hipHostFree(b);
     if (net->cap_stream) (void)hipStreamDestroy(net->cap_stream);
     delete net;
 }
@@ -956,6 +981,384 @@ extern "C" dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h,
         drop_graphs(net);
     }
     return rc;
+}
+
+// ---------------------------------------------------------------- placement (layer on CPU or GPU)
+//
+// The paper's offload search (Sec. 3.3, Sec. 4) decides loop by loop whether
+// a loop runs on the GPU and inserts the copies its transfer rule (Sec. 3.2)
+// implies.  Here the unit is one layer: a gene byte per layer picks the GPU
+// kernels or the host FP32 layer code (cpu_layers.cpp), and each layer output
+// crosses at most once, right after the layer that produces it, when a layer
+// on the other side reads it.
+
+static bool op_on_gpu(const Op &op, const unsigned char *gene)
+{
+    return gene[op.kind == OP_CONV ? op.conv : op.layer] != 0;
+}
+
+struct Crossings {
+    std::vector<char> on_gpu;   // per value: produced by a GPU layer (value 0 is the host image)
+    std::vector<char> to_dev;   // host-produced value that a GPU layer reads
+    std::vector<char> to_host;  // GPU-produced value that a host layer reads
+    bool x_to_dev = false;      // a GPU layer reads the image
+    bool y_from_dev = false;    // a GPU layer produces the result
+};
+
+static Crossings crossings(const Plan &p, const unsigned char *gene)
+{
+    Crossings c;
+    const size_t nv = p.vals.size();
+    c.on_gpu.assign(nv, 0);
+    c.to_dev.assign(nv, 0);
+    c.to_host.assign(nv, 0);
+    for (const Op &op : p.ops) c.on_gpu[op.out] = op_on_gpu(op, gene);
+    for (const Op &op : p.ops) {
+        const bool g = op_on_gpu(op, gene);
+        for (int v : {op.in, op.in2}) {
+            if (v < 0) continue;
+            if (v == 0) {
+                if (g) c.x_to_dev = true;
+            } else if (g && !c.on_gpu[v]) {
+                c.to_dev[v] = 1;
+            } else if (!g && c.on_gpu[v]) {
+                c.to_host[v] = 1;
+            }
+        }
+    }
+    c.y_from_dev = c.on_gpu[p.out_val] != 0;
+    return c;
+}
+
+static size_t tensor_bytes(const Plan &p, int v)
+{
+    const Value &x = p.vals[v];
+    return (size_t)p.batch * x.h * x.w * x.cp * sizeof(float);
+}
+
+static dn_status placed_check(const dn_net *net, const unsigned char *gene, int gene_len)
+{
+    if (net->o.dtype != DN_F32) return fail(DN_EUNSUPPORTED, "layer placement needs an FP32 net");
+    if (net->o.mode != DN_MODE_RESIDENT) return fail(DN_EUNSUPPORTED, "layer placement needs a resident-mode net");
+    if (!gene) return DN_OK;
+    if (gene_len != (int)net->L.size())
+        return fail(DN_EINVAL, "gene has %d values, the net has %zu layers", gene_len, net->L.size());
+    for (int i = 0; i < gene_len; ++i)
+        if (gene[i] > 1) return fail(DN_EINVAL, "gene value %d at layer %d is not 0 or 1", (int)gene[i], i);
+    return DN_OK;
+}
+
+// Arena bound for every gene: all values (the all-host plan has every one),
+// the larger split-K scratch of the unfused and fully fused plans (a conv is
+// either), and the image / result staging.
+static dn_status placed_bytes(const dn_net *net, int batch, int h, int w, size_t *bytes)
+{
+    std::vector<unsigned char> g0(net->L.size(), 0), g1(net->L.size(), 1);
+    Plan p0, p1;
+    STCHK(make_plan(net, F32, DN_MODE_RESIDENT, batch, h, w, &p0, -1, g0.data()));
+    STCHK(make_plan(net, F32, DN_MODE_RESIDENT, batch, h, w, &p1, -1, g1.data()));
+    const size_t staging = p0.total - (p0.ws_off + p0.ws_bytes);
+    *bytes = p0.ws_off + std::max(p0.ws_bytes, p1.ws_bytes) + staging;
+    return DN_OK;
+}
+
+// Host copy of every conv's folded FP32 weights, read back from the device
+// once (weights are defined once per load, Sec. 3.2) and reordered from the
+// packed GEMM layout into the host conv's blocked layout.
+static dn_status ensure_cpu_weights(dn_net *net)
+{
+    std::lock_guard<std::mutex> g(net->mu);
+    for (size_t i = 0; i < net->L.size(); ++i) {
+        if (net->L[i].kind != DN_CONV) continue;
+        ConvWeights &cw = net->cw[i];
+        if (!cw.cpu_w.empty()) continue;
+        const dn_layer_desc &d = net->L[i];
+        const int R = d.ksize, S = d.ksize, cin_p = cw.cin_p, cout_p = cw.cout_p, k_pad = cw.k_pad;
+        std::vector<float> packed((size_t)cout_p * k_pad), bias(cout_p);
+        HIPCHK(hipMemcpy(packed.data(), cw.w, packed.size() * sizeof(float), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(bias.data(), cw.bias, bias.size() * sizeof(float), hipMemcpyDeviceToHost));
+        const bool compact = i == 0 && first_eligible(net, F32);
+        const int CP = first_cp(cw.cin), CB = kblock_ch(F32, cin_p, R * S);
+        auto wval = [&](int co, int r, int s, int c) -> float {
+            size_t k;
+            if (compact) {
+                if (c >= CP) return 0.0f;
+                k = (size_t)r * 16 + s * CP + c;
+            } else {
+                const int cb = c / CB;
+                k = (size_t)(cb * R * S + r * S + s) * CB + (c - cb * CB);
+            }
+            return packed[(size_t)co * k_pad + k];
+        };
+        std::vector<float> blocked((size_t)cout_p * R * S * cin_p);
+        dncpu::pack_weights(wval, cout_p, R, S, cin_p, blocked.data());
+        cw.cpu_w.swap(blocked);
+        cw.cpu_b.swap(bias);
+    }
+    return DN_OK;
+}
+
+static void cpu_op(const dn_net *net, const Plan &p, const Op &op, const std::vector<unsigned char *> &hv)
+{
+    float *out = (float *)hv[op.out];
+    const float *in = (const float *)hv[op.in];
+    if (op.kind == OP_CONV) {  // never fused: fusion needs both layers on the GPU
+        const dn_layer_desc &d = net->L[op.conv];
+        const ConvWeights &cw = net->cw[op.conv];
+        dncpu::conv(in, p.batch, op.H, op.W, op.cin_p, cw.cpu_w.data(), cw.cpu_b.data(), op.cout_p, d.ksize, d.ksize,
+                    d.stride, d.pad, d.activation, net->o.leaky_slope, out, op.Ho, op.Wo);
+    } else if (op.kind == OP_POOL) {
+        const dn_layer_desc &d = net->L[op.layer];
+        const Value &vi = p.vals[op.in];
+        dncpu::maxpool(in, p.batch, vi.h, vi.w, vi.cp, d.ksize, d.stride, out, op.Ho, op.Wo);
+    } else {
+        dncpu::add(in, (const float *)hv[op.in2], out, tensor_bytes(p, op.out) / sizeof(float));
+    }
+}
+
+static dn_status forward_placed(dn_net *net, const unsigned char *gene, const float *x, int batch, int h, int w,
+                                float *y, double timeout_s, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    STCHK(check_ready(net, true));
+    STCHK(check_dims(net, batch, h, w));
+    if (!x || !y) return fail(DN_EINVAL, "x/y are NULL");
+    if (is_device_ptr(x) || is_device_ptr(y)) return fail(DN_EINVAL, "the placed forward takes host x/y");
+    if (!net->arena) return fail(DN_ESTATE, "no arena bound");
+    size_t need = 0;
+    STCHK(placed_bytes(net, batch, h, w, &need));
+    if (net->arena_bytes < need) return fail(DN_ENOMEM, "arena has %zu bytes, placement needs %zu", net->arena_bytes, need);
+    STCHK(ensure_cpu_weights(net));
+    Plan p;
+    STCHK(make_plan(net, F32, DN_MODE_RESIDENT, batch, h, w, &p, -1, gene));
+    const Crossings c = crossings(p, gene);
+    std::vector<unsigned char *> *hv;
+    {
+        std::lock_guard<std::mutex> g(net->mu);
+        hv = &net->host_place[std::make_tuple(batch, h, w)];
+        if (hv->empty()) {
+            for (size_t v = 0; v < p.vals.size(); ++v) {
+                unsigned char *b = nullptr;
+                if (hipHostMalloc((void **)&b, std::max<size_t>(tensor_bytes(p, (int)v), 16), hipHostMallocDefault) !=
+                    hipSuccess) {
+                    for (unsigned char *q : *hv) (void)hipHostFree(q);
+                    hv->clear();
+                    return fail(DN_ENOMEM, "pinned host activations");
+                }
+                hv->push_back(b);
+            }
+        }
+    }
+    char *base = (char *)net->arena;
+    const Value &v0 = p.vals[0];
+    const float *xdev = (const float *)(base + p.xin_off);
+    if (c.x_to_dev) {
+        HIPCHK(hipMemcpyAsync(base + p.xin_off, x, (size_t)batch * v0.c * h * w * sizeof(float),
+                              hipMemcpyHostToDevice, s));
+        if (!p.ops[0].first) HIPCHK(launch_ingest(F32, xdev, batch, v0.c, h, w, v0.cp, 1.0f, base + v0.off, s));
+    } else {
+        dncpu::ingest(x, batch, v0.c, h, w, v0.cp, (float *)(*hv)[0]);
+    }
+    bool pending = false;  // device->host copies not waited for yet
+    for (const Op &op : p.ops) {
+        if (op_on_gpu(op, gene)) {
+            STCHK(enqueue_op(net, p, op, base, s, false, -1, 0, xdev));
+            if (c.to_host[op.out]) {
+                HIPCHK(hipMemcpyAsync((*hv)[op.out], base + p.vals[op.out].off, tensor_bytes(p, op.out),
+                                      hipMemcpyDeviceToHost, s));
+                pending = true;
+            }
+        } else {
+            if (pending) {
+                HIPCHK(hipStreamSynchronize(s));
+                pending = false;
+            }
+            cpu_op(net, p, op, *hv);
+            if (c.to_dev[op.out])
+                HIPCHK(hipMemcpyAsync(base + p.vals[op.out].off, (*hv)[op.out], tensor_bytes(p, op.out),
+                                      hipMemcpyHostToDevice, s));
+        }
+        if (timeout_s > 0.0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s) {
+            (void)hipStreamSynchronize(s);
+            return fail(DN_ETIMEDOUT, "placed forward passed its %.3f s limit after layer %d", timeout_s, op.layer);
+        }
+    }
+    const Value &vo = p.vals[p.out_val];
+    if (c.y_from_dev) {
+        HIPCHK(launch_egress(F32, base + vo.off, batch, vo.c, vo.h, vo.w, vo.cp, 1.0f, (float *)(base + p.yout_off), s));
+        HIPCHK(hipMemcpyAsync(y, base + p.yout_off, (size_t)batch * vo.c * vo.h * vo.w * sizeof(float),
+                              hipMemcpyDeviceToHost, s));
+    } else {
+        if (pending) HIPCHK(hipStreamSynchronize(s));
+        dncpu::egress((const float *)(*hv)[p.out_val], batch, vo.c, vo.h, vo.w, vo.cp, y);
+    }
+    // also waits for host->device copies still reading the pinned host buffers
+    HIPCHK(hipStreamSynchronize(s));
+    return DN_OK;
+}
+
+extern "C" dn_status dn_placed_arena_bytes(const dn_net *net, int batch, int h, int w, size_t *bytes)
+{
+    if (!net || !bytes) return fail(DN_EINVAL, "NULL argument");
+    STCHK(placed_check(net, nullptr, 0));
+    return placed_bytes(net, batch, h, w, bytes);
+}
+
+extern "C" dn_status dn_placed_transfers(const dn_net *net, const unsigned char *gene, int gene_len, int batch, int h,
+                                         int w, int *h2d, int *d2h, size_t *h2d_bytes, size_t *d2h_bytes)
+{
+    if (!net || !gene) return fail(DN_EINVAL, "NULL argument");
+    STCHK(placed_check(net, gene, gene_len));
+    Plan p;
+    STCHK(make_plan(net, F32, DN_MODE_RESIDENT, batch, h, w, &p, -1, gene));
+    const Crossings c = crossings(p, gene);
+    int nh = 0, nd = 0;
+    size_t bh = 0, bd = 0;
+    if (c.x_to_dev) {
+        ++nh;
+        bh += (size_t)batch * p.vals[0].c * h * w * sizeof(float);
+    }
+    if (c.y_from_dev) {
+        const Value &vo = p.vals[p.out_val];
+        ++nd;
+        bd += (size_t)batch * vo.c * vo.h * vo.w * sizeof(float);
+    }
+    for (size_t v = 0; v < p.vals.size(); ++v) {
+        if (c.to_dev[v]) { ++nh; bh += tensor_bytes(p, (int)v); }
+        if (c.to_host[v]) { ++nd; bd += tensor_bytes(p, (int)v); }
+    }
+    if (h2d) *h2d = nh;
+    if (d2h) *d2h = nd;
+    if (h2d_bytes) *h2d_bytes = bh;
+    if (d2h_bytes) *d2h_bytes = bd;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_forward_placed(dn_net *net, const unsigned char *gene, int gene_len, const float *x, int batch,
+                                       int h, int w, float *y, double timeout_s, void *stream)
+{
+    if (!net || !gene) return fail(DN_EINVAL, "NULL argument");
+    STCHK(placed_check(net, gene, gene_len));
+    if (hipSetDevice(net->o.device) != hipSuccess) return fail(DN_EHIP, "hipSetDevice");
+    return forward_placed(net, gene, x, batch, h, w, y, timeout_s, (hipStream_t)stream);
+}
+
+extern "C" dn_status dn_cpu_conv2d(const dn_conv_desc *d, const float *x, const float *w, const float *bias, float *y)
+{
+    if (!d || !x || !w || !bias || !y) return fail(DN_EINVAL, "NULL argument");
+    if (d->dtype != DN_F32 || d->pool || d->residual || d->input_nchw)
+        return fail(DN_EUNSUPPORTED, "host conv: FP32, no fused pool / residual, NHWC input only");
+    if (d->batch <= 0 || d->in_h <= 0 || d->in_w <= 0 || d->in_c <= 0 || d->cout <= 0 || d->ksize <= 0 ||
+        d->stride <= 0 || d->pad < 0)
+        return fail(DN_EINVAL, "bad conv geometry");
+    if (d->activation != DN_ACT_LINEAR && d->activation != DN_ACT_LEAKY) return fail(DN_EINVAL, "unknown activation");
+    const int Ho = out_side_conv(d->in_h, d->ksize, d->stride, d->pad);
+    const int Wo = out_side_conv(d->in_w, d->ksize, d->stride, d->pad);
+    if (Ho <= 0 || Wo <= 0) return fail(DN_EINVAL, "input too small for the filter");
+    const int cin_p = cpad(F32, d->in_c), cout_p = cpad(F32, d->cout), k = d->ksize;
+    auto wval = [&](int co, int r, int s, int c) -> float {
+        if (co >= d->cout || c >= d->in_c) return 0.0f;
+        return w[(((size_t)co * d->in_c + c) * k + r) * k + s];
+    };
+    std::vector<float> blocked((size_t)cout_p * k * k * cin_p), b(cout_p, 0.0f);
+    dncpu::pack_weights(wval, cout_p, k, k, cin_p, blocked.data());
+    std::copy(bias, bias + d->cout, b.begin());
+    dncpu::conv(x, d->batch, d->in_h, d->in_w, cin_p, blocked.data(), b.data(), cout_p, k, k, d->stride, d->pad,
+                d->activation, d->leaky_slope, y, Ho, Wo);
+    return DN_OK;
+}
+
+extern "C" dn_status dn_cpu_maxpool(const dn_pool_desc *d, const float *x, float *y)
+{
+    if (!d || !x || !y) return fail(DN_EINVAL, "NULL argument");
+    if (d->dtype != DN_F32) return fail(DN_EUNSUPPORTED, "host max pool: FP32 only");
+    if (d->batch <= 0 || d->h <= 0 || d->w <= 0 || d->c <= 0 || d->size <= 0 || d->stride <= 0)
+        return fail(DN_EINVAL, "bad pool geometry");
+    dncpu::maxpool(x, d->batch, d->h, d->w, cpad(F32, d->c), d->size, d->stride, y, out_side_pool(d->h, d->stride),
+                   out_side_pool(d->w, d->stride));
+    return DN_OK;
+}
+
+// ---------------------------------------------------------------- GA placement search
+
+static dn_status ga_params(const dn_ga_params *p, int L, dnga::Params *out)
+{
+    if (!p) return fail(DN_EINVAL, "GA parameters are NULL");
+    if (L < 1) return fail(DN_EINVAL, "gene length %d < 1", L);
+    if (p->population < 1 || p->generations < 1)
+        return fail(DN_EINVAL, "population %d / generations %d must be >= 1", p->population, p->generations);
+    if (!(p->crossover >= 0.0 && p->crossover <= 1.0) || !(p->mutation >= 0.0 && p->mutation <= 1.0))
+        return fail(DN_EINVAL, "crossover / mutation rates must lie in [0, 1]");
+    if (!(p->timeout_s > 0.0) || !(p->penalty_s > 0.0)) return fail(DN_EINVAL, "timeout and penalty must be > 0");
+    *out = dnga::Params{p->population, p->generations, p->crossover, p->mutation, p->timeout_s, p->penalty_s,
+                        (uint64_t)p->seed};
+    return DN_OK;
+}
+
+extern "C" dn_status dn_ga_next_generation(const dn_ga_params *p, int gene_len, const unsigned char *pop,
+                                           const double *seconds, unsigned char *next, unsigned long long *rng_state)
+{
+    dnga::Params gp;
+    STCHK(ga_params(p, gene_len, &gp));
+    if (!pop || !seconds || !next || !rng_state) return fail(DN_EINVAL, "NULL argument");
+    for (int i = 0; i < gp.population; ++i)
+        if (!(seconds[i] > 0.0) || std::isinf(seconds[i])) return fail(DN_EINVAL, "time %d is not positive and finite", i);
+    uint64_t st = *rng_state;
+    dnga::next_generation(gp, gene_len, pop, seconds, next, &st);
+    *rng_state = st;
+    return DN_OK;
+}
+
+extern "C" dn_status dn_ga_search(const dn_ga_params *p, int gene_len, dn_ga_measure_fn measure, void *user,
+                                  unsigned char *best_gene, double *gen_best, dn_ga_result *res)
+{
+    dnga::Params gp;
+    STCHK(ga_params(p, gene_len, &gp));
+    if (!measure || !best_gene) return fail(DN_EINVAL, "NULL argument");
+    dnga::Result r;
+    auto fn = [&](const uint8_t *g, double timeout) { return measure(g, gene_len, timeout, user); };
+    if (!dnga::search(gp, gene_len, fn, best_gene, gen_best, &r)) return fail(DN_ESTATE, "the measurement aborted the search");
+    if (res) *res = dn_ga_result{r.best_seconds, r.evaluations, r.memo_hits};
+    return DN_OK;
+}
+
+extern "C" dn_status dn_ga_place(dn_net *net, const dn_ga_params *p, const float *x, int batch, int h, int w, float *y,
+                                 int reps, void *stream, unsigned char *best_gene, double *gen_best, dn_ga_result *res)
+{
+    if (!net || !best_gene) return fail(DN_EINVAL, "NULL argument");
+    const int L = (int)net->L.size();
+    dnga::Params gp;
+    STCHK(ga_params(p, L, &gp));
+    STCHK(placed_check(net, nullptr, 0));
+    if (reps < 1) return fail(DN_EINVAL, "reps %d < 1", reps);
+    HIPCHK(hipSetDevice(net->o.device));
+    hipStream_t s = (hipStream_t)stream;
+    for (unsigned char v : {1, 0}) {  // warm-up: host buffers, host weights, kernels
+        std::vector<unsigned char> g(L, v);
+        STCHK(forward_placed(net, g.data(), x, batch, h, w, y, 0.0, s));
+    }
+    dn_status err = DN_OK;
+    auto fn = [&](const uint8_t *g, double timeout) -> double {
+        std::vector<double> t;
+        for (int r = 0; r < reps; ++r) {
+            const auto a = std::chrono::steady_clock::now();
+            const dn_status st = forward_placed(net, g, x, batch, h, w, y, timeout, s);
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+            if (st == DN_ETIMEDOUT) return -1.0;
+            if (st != DN_OK) {
+                err = st;
+                return std::nan("");
+            }
+            t.push_back(dt);
+        }
+        std::sort(t.begin(), t.end());
+        return t[t.size() / 2];
+    };
+    dnga::Result r;
+    if (!dnga::search(gp, L, fn, best_gene, gen_best, &r)) return err;  // dn_last_error holds the forward's message
+    if (res) *res = dn_ga_result{r.best_seconds, r.evaluations, r.memo_hits};
+    return DN_OK;
 }
 
 // ---------------------------------------------------------------- autotuner

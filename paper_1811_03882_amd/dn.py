@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdn.so")
 
-DN_OK, DN_EINVAL, DN_ENOMEM, DN_EHIP, DN_ESTATE, DN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DN_OK, DN_EINVAL, DN_ENOMEM, DN_EHIP, DN_ESTATE, DN_EUNSUPPORTED, DN_ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6
 F32, BF16, FP8 = 0, 1, 2
 RESIDENT, PER_LAYER = 0, 1
 CONV, MAXPOOL, SHORTCUT = 0, 1, 2
@@ -59,6 +59,19 @@ class PoolDesc(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int), ("h", ctypes.c_int), ("w", ctypes.c_int), ("c", ctypes.c_int),
                 ("size", ctypes.c_int), ("stride", ctypes.c_int), ("dtype", ctypes.c_int)]
 
+
+class GaParams(ctypes.Structure):
+    _fields_ = [("population", ctypes.c_int), ("generations", ctypes.c_int), ("crossover", ctypes.c_double),
+                ("mutation", ctypes.c_double), ("timeout_s", ctypes.c_double), ("penalty_s", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong)]
+
+
+class GaResult(ctypes.Structure):
+    _fields_ = [("best_seconds", ctypes.c_double), ("evaluations", ctypes.c_int), ("memo_hits", ctypes.c_int)]
+
+
+GA_MEASURE = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int, ctypes.c_double,
+                              ctypes.c_void_p)
 
 _vp, _i, _sz, _f, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_float, ctypes.c_double
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -106,6 +119,15 @@ SIGNATURES = {
     "dn_nightmare": (_i, [_vp, _i, _vp, _i, _i, _i, _f, _i, _vp]),
     "dn_nightmare_arena": (_i, [_vp, _vp, _sz, _i, _vp, _i, _i, _i, _f, _i, _vp]),
     "dn_autotune_backward": (_i, [_vp, _i, _i, _i, _i, _vp]),
+    "dn_placed_arena_bytes": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "dn_placed_transfers": (_i, [_vp, _vp, _i, _i, _i, _i, _ip, _ip, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    "dn_forward_placed": (_i, [_vp, _vp, _i, _vp, _i, _i, _i, _vp, _d, _vp]),
+    "dn_cpu_conv2d": (_i, [ctypes.POINTER(ConvDesc), _vp, _vp, _vp, _vp]),
+    "dn_cpu_maxpool": (_i, [ctypes.POINTER(PoolDesc), _vp, _vp]),
+    "dn_ga_next_generation": (_i, [ctypes.POINTER(GaParams), _i, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "dn_ga_search": (_i, [ctypes.POINTER(GaParams), _i, GA_MEASURE, _vp, _vp, _vp, ctypes.POINTER(GaResult)]),
+    "dn_ga_place": (_i, [_vp, ctypes.POINTER(GaParams), _vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp,
+                         ctypes.POINTER(GaResult)]),
     "dn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -341,6 +363,41 @@ class Net:
         check(LIB.dn_nightmare_arena(self._h, ptr(arena), nbytes, layer, ptr(x), batch, h, w, rate, iters,
                                      stream_handle(stream)))
 
+    # ---- layer placement between the host CPU and the GPU (genes: one 0/1 per layer)
+
+    def placed_arena_bytes(self, batch: int, h: int, w: int) -> int:
+        n = _sz()
+        check(LIB.dn_placed_arena_bytes(self._h, batch, h, w, ctypes.byref(n)))
+        return n.value
+
+    def placed_transfers(self, gene, batch: int, h: int, w: int):
+        """(h2d copies, d2h copies, h2d bytes, d2h bytes) per placed forward."""
+        g = _gene(gene)
+        a, b, c, d = _i(), _i(), _sz(), _sz()
+        check(LIB.dn_placed_transfers(self._h, g.ctypes.data, len(g), batch, h, w, ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def forward_placed(self, gene, x: np.ndarray, batch: int, h: int, w: int, y: np.ndarray, timeout_s: float = 0.0,
+                       stream=None) -> None:
+        """Placed forward on host NCHW FP32 arrays x -> y."""
+        g = _gene(gene)
+        assert x.dtype == np.float32 and x.flags.c_contiguous and y.dtype == np.float32 and y.flags.c_contiguous
+        check(LIB.dn_forward_placed(self._h, g.ctypes.data, len(g), x.ctypes.data, batch, h, w, y.ctypes.data,
+                                    float(timeout_s), stream_handle(stream)))
+
+    def ga_place(self, params: "GaParams", x: np.ndarray, batch: int, h: int, w: int, y: np.ndarray, reps: int = 3,
+                 stream=None):
+        """The GA over this net's placements; returns (best gene, per-generation best seconds, GaResult)."""
+        L = len(self.layers)
+        best = np.zeros(L, dtype=np.uint8)
+        gen = np.zeros(params.generations, dtype=np.float64)
+        res = GaResult()
+        assert x.dtype == np.float32 and y.dtype == np.float32
+        check(LIB.dn_ga_place(self._h, ctypes.byref(params), x.ctypes.data, batch, h, w, y.ctypes.data, reps,
+                              stream_handle(stream), best.ctypes.data, gen.ctypes.data, ctypes.byref(res)))
+        return best, gen, res
+
     def layer_plan(self, layer: int, batch: int, h: int, w: int):
         v = [_i() for _ in range(4)]
         check(LIB.dn_layer_plan(self._h, layer, batch, h, w, *[ctypes.byref(x) for x in v]))
@@ -416,3 +473,57 @@ def maxpool_backward(batch, h, w, c, size, stride, dtype, x, dy, accumulate, dx,
 
 def leaky_backward(dtype, count, a, dy, slope, dx, stream=None):
     check(LIB.dn_leaky_backward(dtype, count, ptr(a), ptr(dy), slope, ptr(dx), stream_handle(stream)))
+
+
+# ------------------------------------------------------------ placement search (host logic)
+
+
+def _gene(gene) -> np.ndarray:
+    g = np.ascontiguousarray(np.asarray(gene, dtype=np.uint8))
+    assert g.ndim == 1
+    return g
+
+
+def ga_params(population=30, generations=20, crossover=0.9, mutation=0.05, timeout_s=180.0, penalty_s=1000.0,
+              seed=0) -> GaParams:
+    """GA parameters; the defaults are the paper's (M 30, T 20, Pc 0.9, Pm 0.05,
+    a 3-minute limit scored as 1000 s)."""
+    return GaParams(population, generations, crossover, mutation, timeout_s, penalty_s, seed)
+
+
+def ga_next_generation(params: GaParams, pop: np.ndarray, seconds: np.ndarray, rng_state: int):
+    """One generation step; returns (next population, new rng state)."""
+    pop = np.ascontiguousarray(pop, dtype=np.uint8)
+    sec = np.ascontiguousarray(seconds, dtype=np.float64)
+    nxt = np.zeros_like(pop)
+    st = ctypes.c_ulonglong(rng_state)
+    check(LIB.dn_ga_next_generation(ctypes.byref(params), pop.shape[1], pop.ctypes.data, sec.ctypes.data,
+                                    nxt.ctypes.data, ctypes.byref(st)))
+    return nxt, st.value
+
+
+def ga_search(params: GaParams, gene_len: int, measure):
+    """GA with a Python measurement measure(gene: np.ndarray, timeout_s) -> seconds;
+    returns (best gene, per-generation best seconds, GaResult)."""
+    def cb(gp, n, timeout, user):
+        return float(measure(np.ctypeslib.as_array(gp, shape=(n,)).copy(), timeout))
+    fn = GA_MEASURE(cb)
+    best = np.zeros(gene_len, dtype=np.uint8)
+    gen = np.zeros(params.generations, dtype=np.float64)
+    res = GaResult()
+    check(LIB.dn_ga_search(ctypes.byref(params), gene_len, fn, None, best.ctypes.data, gen.ctypes.data,
+                           ctypes.byref(res)))
+    return best, gen, res
+
+
+def cpu_conv2d(d: ConvDesc, x: np.ndarray, w: np.ndarray, bias: np.ndarray, y: np.ndarray) -> None:
+    """Host FP32 conv of the placement's CPU side on NHWC (padded) arrays."""
+    for a in (x, w, bias, y):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    check(LIB.dn_cpu_conv2d(ctypes.byref(d), x.ctypes.data, w.ctypes.data, bias.ctypes.data, y.ctypes.data))
+
+
+def cpu_maxpool(batch, h, w, c, size, stride, x: np.ndarray, y: np.ndarray) -> None:
+    d = PoolDesc(batch, h, w, c, size, stride, F32)
+    assert x.dtype == np.float32 and y.dtype == np.float32
+    check(LIB.dn_cpu_maxpool(ctypes.byref(d), x.ctypes.data, y.ctypes.data))
