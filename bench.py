@@ -179,6 +179,54 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print)
             **out}
 
 
+def placement_search(dn, net, params, xh, log=print, population=30, generations=20, reps=3):
+    """The paper's GA offload search (Sec. 3.3, 4; M, T, Pc, Pm, fitness and
+    the timeout penalty of Sec. 5.1.2) over the per-layer CPU/GPU placement of
+    the 9-layer net, FP32, batch 1, 416x416: best gene against all-GPU and
+    all-CPU placements, with the crossings each implies."""
+    H, W = xh.shape[2], xh.shape[3]
+    n = dn.Net(net.layers, net.in_c, H, W, 1, dtype=dn.F32, leaky_slope=net.leaky_slope, bn_eps=net.bn_eps)
+    n.load_params(params)
+    import torch
+    arena = torch.empty(max(n.placed_arena_bytes(1, H, W), n.arena_bytes(1, H, W)), dtype=torch.uint8, device="cuda")
+    n.bind_arena(arena)
+    y = np.empty((1,) + n.output_shape(H, W), np.float32)
+    L = len(net.layers)
+
+    def timed(gene, k=5):
+        n.forward_placed(gene, xh, 1, H, W, y)
+        t = []
+        for _ in range(k):
+            t0 = time.perf_counter()
+            n.forward_placed(gene, xh, 1, H, W, y)
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t))
+    all_gpu, all_cpu = np.ones(L, np.uint8), np.zeros(L, np.uint8)
+    t_gpu, t_cpu = timed(all_gpu), timed(all_cpu)
+    log("[bench] placement: all-GPU %.3f ms, all-CPU %.3f ms" % (t_gpu * 1e3, t_cpu * 1e3))
+    p = dn.ga_params(population=population, generations=generations, crossover=0.9, mutation=0.05,
+                     timeout_s=180.0, penalty_s=1000.0, seed=1)
+    t0 = time.perf_counter()
+    best, gen, res = n.ga_place(p, xh, 1, H, W, y, reps=reps)
+    wall = time.perf_counter() - t0
+    t_best = timed(best)
+    xfer = n.placed_transfers(best, 1, H, W)
+    log("[bench] placement GA: best %s %.3f ms after %d evaluations (%.1f s)" %
+        ("".join(map(str, best)), t_best * 1e3, res.evaluations, wall))
+    out = {"workload": "placement search (GA of Sec. 3.3/4/5.1.2) over the 15 layers of the 9-layer net, f32 b1 "
+                       "416x416: each gene's layers on the GPU (1) or the host CPU (0), copies by the Sec. 3.2 rule",
+           "gene_length": L, "population": population, "generations": generations, "crossover": 0.9,
+           "mutation": 0.05, "fitness": "time^-0.5", "reps_per_gene": reps,
+           "host_threads": int(os.environ.get("DN_CPU_THREADS", os.environ.get("OMP_NUM_THREADS", "0")) or 0) or None,
+           "best_gene": "".join(map(str, best)), "best_ms": t_best * 1e3, "best_ms_in_search": res.best_seconds * 1e3,
+           "generation_best_ms": [g * 1e3 for g in gen], "evaluations": res.evaluations, "memo_hits": res.memo_hits,
+           "search_wall_s": wall, "all_gpu_ms": t_gpu * 1e3, "all_cpu_ms": t_cpu * 1e3,
+           "speedup_best_over_all_cpu": t_cpu / t_best,
+           "best_gene_copies": {"h2d": xfer[0], "d2h": xfer[1], "h2d_bytes": xfer[2], "d2h_bytes": xfer[3]}}
+    n.close()
+    return out
+
+
 def traffic_from_profiles(layer_key: str, tile: int):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     PMC summary, only if it was taken on the current kernel source and with
@@ -270,6 +318,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--no-ga", action="store_true", help="skip the GA placement search line")
+    ap.add_argument("--placement-driver", action="store_true",
+                    help="run only the GA placement search (9-layer f32 b1 416x416) and print its JSON")
     ap.add_argument("--pmc-driver", action="store_true",
                     help="run only the dominant conv kernel (5 launches) and a 256 MiB device copy, "
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -317,6 +368,10 @@ def main():
     x = torch.from_numpy(synth.make_input(net, B, synth.SEED_PLAIN).astype(np.float32)).cuda()
     stream = torch.cuda.Stream()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    if args.placement_driver:
+        print(json.dumps(placement_search(dn, net, params, np.ascontiguousarray(x[:1].cpu().numpy()), log=log)))
+        return
 
     if args.residual_driver:
         rnet = synth.residual52()
@@ -588,6 +643,8 @@ def main():
                           "images_per_s": 1e3 / float(np.mean(lat)), "p50_ms": float(np.percentile(lat, 50)),
                           "p99_ms": float(np.percentile(lat, 99))})
         n4.close()
+        if not args.no_ga:
+            secondary.append(placement_search(dn, net, params, xh, log=log))
 
     serving_res = None
     if not args.no_serving and not args.no_secondary:
