@@ -478,6 +478,21 @@ dn_status dn_ga_search(const dn_ga_params *p, int gene_len, dn_ga_measure_fn mea
 dn_status dn_ga_place(dn_net *net, const dn_ga_params *p, const float *x, int batch, int h, int w, float *y,
                       int reps, void *stream, unsigned char *best_gene, double *gen_best, dn_ga_result *res);
 
+/* dn_detect without a workspace argument, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The decode's scratch is a fixed array of 16 MiB
+ * inside the library, one per GPU, held until the process ends; the call
+ * allocates nothing (no hipMalloc / hipFree / allocating library routine)
+ * and runs on the current device.  Inputs needing more than 16 MiB of
+ * scratch (batch*classes*h*w*anchors*4 rounded up to 256 bytes, plus
+ * batch*h*w*anchors*16) are rejected with DN_EINVAL.  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be ordered by the caller.  Other
+ * arguments, outputs and errors as dn_detect. */
+dn_status dn_detect_noalloc(const float *y, int batch, int anchors, int classes, int h, int w,
+                            const float *anchor_wh, float thresh, float nms_thresh, int max_det,
+                            float *dets, int *det_index, int *counts, void *stream);
+
 /* Measurement helper: the matrix-core throughput the device sustains for the
  * MFMA instruction the convolutions of `dtype` use (16x16x4 FP32, 16x16x32
  * BF16, 16x16x128 FP8), from a kernel that only multiplies (8 waves per SIMD,

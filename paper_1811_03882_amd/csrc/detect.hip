@@ -19,6 +19,8 @@
 // states, so threshold and overlap decisions are reproducible.
 #include "dn_kernels.h"
 
+#include <mutex>
+
 #pragma clang fp contract(off)
 
 namespace dnk {
@@ -138,6 +140,35 @@ size_t detect_nms_lds(int boxes)
     int P = 1;
     while (P < boxes) P <<= 1;
     return (size_t)P * 25;
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// The decoded scores and boxes of dn_detect_noalloc live here instead of in a
+// caller workspace.  Each GPU the library runs on holds its own copy for the
+// life of the process; calls on one GPU share it.  In host code the array's
+// name is not a device address: its address is taken once per device with
+// hipGetSymbolAddress (that device current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[DETECT_NOALLOC_BYTES];
+
+hipError_t detect_scratch(void **ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_detect(const DetectArgs &a, hipStream_t s)

@@ -155,6 +155,12 @@ struct DetectArgs {
 };
 hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
 size_t detect_nms_lds(int boxes);
+// Fixed device scratch of the allocation-free detection entry point: one
+// file-scope array per GPU (detect.hip), DETECT_NOALLOC_BYTES long.
+// detect_scratch() returns its device address on the current device (looked
+// up once per device, then cached).
+constexpr size_t DETECT_NOALLOC_BYTES = (size_t)16 << 20;
+hipError_t detect_scratch(void **ptr);
 
 // One Jacobi iteration of the Laplace equation on an [n][m] FP64 grid
 // (jacobi.hip); max_change (device, may be NULL) receives the bits of the

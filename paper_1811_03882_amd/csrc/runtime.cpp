@@ -1591,6 +1591,22 @@ extern "C" dn_status dn_detect(const float *y, int batch, int anchors, int class
     return DN_OK;
 }
 
+extern "C" dn_status dn_detect_noalloc(const float *y, int batch, int anchors, int classes, int h, int w,
+                                       const float *anchor_wh, float thresh, float nms_thresh, int max_det,
+                                       float *dets, int *det_index, int *counts, void *stream)
+{
+    STCHK(detect_check(batch, anchors, classes, h, w));
+    size_t need = 0;
+    STCHK(dn_detect_workspace(batch, anchors, classes, h, w, &need));
+    if (need > DETECT_NOALLOC_BYTES)
+        return fail(DN_EINVAL, "detect (no allocation): the decode needs %zu bytes, the fixed scratch holds %zu; "
+                    "use dn_detect with a workspace", need, DETECT_NOALLOC_BYTES);
+    void *ws = nullptr;
+    HIPCHK(detect_scratch(&ws));
+    return dn_detect(y, batch, anchors, classes, h, w, anchor_wh, thresh, nms_thresh, max_det, ws, need, dets,
+                     det_index, counts, stream);
+}
+
 extern "C" dn_status dn_mfma_peak(int dtype, int device, double *tflops)
 {
     if (!tflops) return fail(DN_EINVAL, "tflops is NULL");

@@ -106,6 +106,8 @@ SIGNATURES = {
     "dn_detect_workspace": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "dn_detect": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_float), _f, _f, _i, _vp, _sz, _vp, _vp,
                        _vp, _vp]),
+    "dn_detect_noalloc": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_float), _f, _f, _i, _vp, _vp, _vp,
+                               _vp]),
     "dn_conv_backward_sizes": (_i, [ctypes.POINTER(ConvDesc), ctypes.POINTER(_sz), ctypes.POINTER(_sz),
                                     ctypes.POINTER(_sz)]),
     "dn_conv_pack_backward": (_i, [ctypes.POINTER(ConvDesc), _dp, _dp, _dp, _dp, _d, _vp, _vp, _vp, _vp]),
@@ -229,6 +231,14 @@ def detect(y, batch, anchors, classes, h, w, anchor_wh, thresh, nms_thresh, max_
     aw = (ctypes.c_float * len(anchor_wh))(*[float(v) for v in anchor_wh])
     check(LIB.dn_detect(ptr(y), batch, anchors, classes, h, w, aw, float(thresh), float(nms_thresh), max_det,
                         ptr(workspace), ws_bytes, ptr(dets), ptr(det_index), ptr(counts), stream_handle(stream)))
+
+
+def detect_noalloc(y, batch, anchors, classes, h, w, anchor_wh, thresh, nms_thresh, max_det, dets, det_index, counts,
+                   stream=None):
+    """dn_detect on the library's fixed per-GPU scratch (no workspace, no allocation)."""
+    aw = (ctypes.c_float * len(anchor_wh))(*[float(v) for v in anchor_wh])
+    check(LIB.dn_detect_noalloc(ptr(y), batch, anchors, classes, h, w, aw, float(thresh), float(nms_thresh), max_det,
+                                ptr(dets), ptr(det_index), ptr(counts), stream_handle(stream)))
 
 
 def mfma_peak(dtype: int, device: int = 0) -> float:
