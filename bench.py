@@ -279,6 +279,183 @@ def summarize_trace(trace_csv: str, min_run: int = 20) -> str:
     return "\n".join(out)
 
 
+API_REPS = 20
+
+
+def api_driver(torch, dn, net, params, x, stream, log=print):
+    """Steady-state host API use per forward, for a rocprofv3 --hip-trace
+    --marker-trace --kernel-trace run: each case runs API_REPS forwards inside
+    one roctx range (warm-up, tuning and graph capture happen before it)."""
+    import ctypes
+    roctx = ctypes.CDLL("librocprofiler-sdk-roctx.so")
+    roctx.roctxRangePushA.argtypes = [ctypes.c_char_p]
+    roctx.roctxMarkA.argtypes = [ctypes.c_char_p]
+    B, H, W = x.shape[0], x.shape[2], x.shape[3]
+
+    def ranged(name, fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        roctx.roctxRangePushA(("%s x%d" % (name, API_REPS)).encode())
+        for _ in range(API_REPS):
+            fn()
+        roctx.roctxRangePop()
+        torch.cuda.synchronize()
+        roctx.roctxMarkA(("%s x%d end" % (name, API_REPS)).encode())
+        log("[api] %s done" % name)
+
+    out_shape = None
+    nb, ab = build_net(dn, torch, net, dn.BF16, B, H, W, params)
+    out_shape = nb.output_shape(H, W)
+    y = torch.empty((B,) + out_shape, dtype=torch.float32, device="cuda")
+    ranged("bf16_b%d_graph_device_io" % B, lambda: nb.forward(x, B, H, W, y, stream))
+    xh = torch.empty(x.shape, dtype=torch.float32, pin_memory=True)
+    xh.copy_(x.cpu())
+    yh = torch.empty(y.shape, dtype=torch.float32, pin_memory=True)
+    xd = torch.empty_like(x)
+
+    def with_pcie():
+        with torch.cuda.stream(stream):
+            xd.copy_(xh, non_blocking=True)
+            nb.forward(xd, B, H, W, y, stream)
+            yh.copy_(y, non_blocking=True)
+    ranged("bf16_b%d_graph_pinned_host_io" % B, with_pcie)
+    nb.close()
+    x1 = x[:1].contiguous()
+    y1 = torch.empty((1,) + out_shape, dtype=torch.float32, device="cuda")
+    n3, a3 = build_net(dn, torch, net, dn.F32, 1, H, W, params)
+    ranged("f32_b1_graph_device_io", lambda: n3.forward(x1, 1, H, W, y1, stream))
+    n3.close()
+    n4, a4 = build_net(dn, torch, net, dn.F32, 1, H, W, params, use_graph=False, tune=False)
+    ranged("f32_b1_eager_device_io", lambda: n4.forward(x1, 1, H, W, y1, stream))
+    n4.close()
+    n5, a5 = build_net(dn, torch, net, dn.F32, 1, H, W, params, use_graph=False, tune=False, mode=dn.PER_LAYER)
+    x1h = np.ascontiguousarray(x1.cpu().numpy())
+    y1h = np.empty((1,) + out_shape, np.float32)
+    ranged("f32_b1_per_layer_transfer", lambda: n5.forward(x1h, 1, H, W, y1h))
+    n5.close()
+
+
+def summarize_api(trace_dir: str) -> str:
+    """Markdown summary of an api_driver run: per roctx range, HIP API calls
+    per forward (copies, synchronisations, allocations, launches), and the
+    GPU timeline of the range's kernels (busy time per forward and the idle
+    gaps between kernels)."""
+    import glob
+    def one(pattern):
+        f = sorted(glob.glob(os.path.join(trace_dir, "**", pattern), recursive=True))
+        if not f:
+            raise SystemExit("no %s under %s" % (pattern, trace_dir))
+        return _csv_rows(f[0])
+    api, marks, kern = one("*hip_api_trace.csv"), one("*marker_api_trace.csv"), one("*kernel_trace.csv")
+    groups = [("graph launch", lambda f: f.startswith("hipGraphLaunch")),
+              ("kernel launch", lambda f: f in ("hipLaunchKernel", "hipExtLaunchKernel", "hipModuleLaunchKernel")
+               or f.startswith("__hipPushCallConfiguration")),
+              ("copy host->device", None), ("copy device->host", None),
+              ("copy (all hipMemcpy*)", lambda f: f.startswith("hipMemcpy")),
+              ("synchronize", lambda f: "Synchronize" in f or f.startswith("hipEventSynchronize")),
+              ("allocate / free", lambda f: f.startswith(("hipMalloc", "hipFree", "hipHostMalloc", "hipHostFree",
+                                                          "hipExtMalloc"))),
+              ("graph capture / instantiate", lambda f: "Capture" in f or "Instantiate" in f)]
+    out = ["| range (%d forwards) | %s | all HIP calls | GPU busy us / fwd | kernels / fwd | idle us / fwd |"
+           % (API_REPS, " | ".join(g[0] for g in groups if g[1] is not None)),
+           "|---|" + "---|" * (sum(1 for g in groups if g[1] is not None) + 4)]
+    ends = {m.get("Function", ""): int(m["Start_Timestamp"]) for m in marks}
+    for m in marks:
+        name = m.get("Function", "")
+        if not name.endswith(" x%d" % API_REPS):
+            continue
+        t0, t1 = int(m["Start_Timestamp"]), int(m["End_Timestamp"])
+        t_end = ends.get(name + " end", t1)  # after the caller's synchronisation: every kernel of the range ran
+        calls = [a["Function"] for a in api if t0 <= int(a["Start_Timestamp"]) <= t1]
+        cells = []
+        for label, pred in groups:
+            if pred is None:
+                continue
+            cells.append("%.2f" % (sum(1 for c in calls if pred(c)) / API_REPS))
+        ks = sorted((int(k["Start_Timestamp"]), int(k["End_Timestamp"])) for k in kern
+                    if t0 <= int(k["Start_Timestamp"]) <= t_end)
+        busy = sum(e - b for b, e in ks)
+        span = (ks[-1][1] - ks[0][0]) if ks else 0
+        out.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (
+            name, " | ".join(cells), len(calls) / API_REPS, busy / 1e3 / API_REPS, len(ks) / API_REPS,
+            (span - busy) / 1e3 / API_REPS))
+    return "\n".join(out)
+
+
+def layer_alg_bytes(net, batch, h, w, esize, in_esize=None):
+    """Algorithmic HBM bytes per conv launch (fused pool included): the input
+    read once, the packed weights once and the (pooled) output written once, in
+    the storage type with 16-byte channel padding; the first conv reads the
+    FP32 NCHW image.  Keyed by the conv's layer index."""
+    import synth
+    seg = 16 // esize
+    pad = lambda c: (c + seg - 1) // seg * seg
+    out, c, hh, ww = {}, net.in_c, h, w
+    L = net.layers
+    for i, l in enumerate(L):
+        if l.kind == synth.CONV:
+            ho = (hh + 2 * l.pad - l.ksize) // l.stride + 1
+            wo = (ww + 2 * l.pad - l.ksize) // l.stride + 1
+            pooled = i + 1 < len(L) and L[i + 1].kind == synth.MAXPOOL and L[i + 1].stride == 2 and L[i + 1].ksize == 2
+            oh, ow = (ho // 2, wo // 2) if pooled else (ho, wo)
+            xin = batch * c * hh * ww * 4 if i == 0 else batch * hh * ww * pad(c) * esize
+            wts = pad(l.cout) * l.ksize * l.ksize * pad(c) * esize
+            out[i] = xin + wts + batch * oh * ow * pad(l.cout) * esize
+            c, hh, ww = l.cout, ho, wo
+        elif l.kind == synth.MAXPOOL:
+            hh, ww = (hh - 1) // l.stride + 1, (ww - 1) // l.stride + 1
+    return out
+
+
+def summarize_pmc_layers(fetch_csv: str, write_csv: str, driver_json: str, launches: int = 5):
+    """HBM bytes per launch of several convs from two rocprofv3 --pmc runs of
+    `bench.py --pmc-driver --pmc-layers ...` (FETCH_SIZE, then WRITE_SIZE, KiB
+    per dispatch), each scaled by what the counter reads for the driver's
+    256 MiB device copy; the last dispatches are the layers' timed launches in
+    the driver's order (fill kernels skipped)."""
+    import synth
+    drv = None
+    for line in open(driver_json):
+        line = line.strip()
+        if line.startswith("{") and "pmc_driver" in line:
+            drv = json.loads(line)
+    layers, kpl = drv["layers"], drv["kernels_per_launch"]
+    net = synth.plain9()
+    alg = layer_alg_bytes(net, 64, 416, 416, 2)
+
+    def load(path, counter):
+        disp = {}
+        for r in _csv_rows(path):
+            if r["Counter_Name"] == counter:
+                d = disp.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])
+                d[1] += float(r["Counter_Value"])
+        return [disp[k] for k in sorted(disp)]
+
+    res = {"kernel_source_hash": kernel_source_hash(), "batch": 64, "image": [3, 416, 416], "dtype": "bf16"}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = load(path, counter)
+        copy = next(v for k, v in d if "copyBuffer" in k)
+        factor = copy * 1024.0 / (256 << 20)
+        convs = [(k, v) for k, v in d if "fillBuffer" not in k]
+        need = sum(launches * n for n in kpl)
+        tail = convs[-need:]
+        pos = 0
+        for layer, n in zip(layers, kpl):
+            chunk = tail[pos:pos + launches * n]
+            pos += launches * n
+            e = per.setdefault(str(layer), {"kernels": sorted({k[:100] for k, _ in chunk}), "factor": {}})
+            e["factor"][counter] = factor
+            e[counter.lower() + "_bytes_per_launch"] = sum(v for _, v in chunk) / launches * 1024.0 / factor
+    for layer, e in per.items():
+        e["hbm_bytes_per_launch"] = e["fetch_size_bytes_per_launch"] + e["write_size_bytes_per_launch"]
+        e["algorithmic_bytes_per_launch"] = alg[int(layer)]
+        e["traffic_over_algorithmic"] = e["hbm_bytes_per_launch"] / alg[int(layer)]
+    res["layers"] = per
+    return res
+
+
 def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, tile: int, launches: int = 5):
     """HBM bytes per launch of the dominant conv from two rocprofv3 --pmc runs
     of `bench.py --pmc-driver` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
@@ -319,6 +496,16 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--no-ga", action="store_true", help="skip the GA placement search line")
+    ap.add_argument("--api-driver", action="store_true",
+                    help="run only the steady-state forwards of api_driver (for rocprofv3 --hip-trace "
+                         "--marker-trace --kernel-trace)")
+    ap.add_argument("--pmc-layers", default="",
+                    help="with --pmc-driver: comma-separated conv layers to launch 5 times each (default: the "
+                         "dominant conv)")
+    ap.add_argument("--summarize-pmc-layers", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "DRIVER_OUTPUT"),
+                    help="print the per-layer HBM-traffic JSON of two --pmc-driver --pmc-layers runs and exit")
+    ap.add_argument("--summarize-api", metavar="ROCPROF_DIR",
+                    help="print the markdown summary of an --api-driver trace directory and exit (no GPU)")
     ap.add_argument("--placement-driver", action="store_true",
                     help="run only the GA placement search (9-layer f32 b1 416x416) and print its JSON")
     ap.add_argument("--pmc-driver", action="store_true",
@@ -337,6 +524,12 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_pmc_layers:
+        print(json.dumps(summarize_pmc_layers(*args.summarize_pmc_layers), indent=1))
+        return
+    if args.summarize_api:
+        print(summarize_api(args.summarize_api))
         return
     if args.summarize_pmc:
         f, w, layer, tile = args.summarize_pmc
@@ -368,6 +561,10 @@ def main():
     x = torch.from_numpy(synth.make_input(net, B, synth.SEED_PLAIN).astype(np.float32)).cuda()
     stream = torch.cuda.Stream()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    if args.api_driver:
+        api_driver(torch, dn, net, params, x, stream, log=log)
+        return
 
     if args.placement_driver:
         print(json.dumps(placement_search(dn, net, params, np.ascontiguousarray(x[:1].cpu().numpy()), log=log)))
@@ -402,12 +599,17 @@ def main():
     if args.pmc_driver:
         flops = conv_flops(net, B, H, W)
         dom = max(flops, key=lambda k: flops[k][0])
+        layers = [int(v) for v in args.pmc_layers.split(",") if v.strip()] or [dom]
         nb.forward(x, B, H, W, torch.empty((B,) + nb.output_shape(H, W), device="cuda"), stream)
         torch.cuda.synchronize()
-        nb.time_layer(dom, B, H, W, 5, stream)
-        torch.cuda.synchronize()
-        print(json.dumps({"pmc_driver": True, "copy_bytes": 256 << 20, "layer": dom,
-                          "plan": nb.layer_plan(dom, B, H, W)}))
+        plans = {}
+        for layer in layers:
+            nb.time_layer(layer, B, H, W, 5, stream)
+            torch.cuda.synchronize()
+            plans[layer] = nb.layer_plan(layer, B, H, W)
+        print(json.dumps({"pmc_driver": True, "copy_bytes": 256 << 20, "layer": dom, "layers": layers,
+                          "kernels_per_launch": [2 if plans[l]["splits"] > 1 else 1 for l in layers],
+                          "plan": plans[dom] if dom in plans else None, "plans": plans}))
         return
     out_shape = nb.output_shape(H, W)
     y = torch.empty((B,) + out_shape, dtype=torch.float32, device="cuda")

@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -140,9 +141,13 @@ struct dn_net {
     // Two instances of each captured forward, launched alternately: a launch
     // then never has to wait for the previous replay of the same instance to
     // retire, so the host can queue the next forward while one runs.
-    struct GraphPair { hipGraphExec_t exec[2] = {nullptr, nullptr}; unsigned next = 0; };
+    struct GraphPair { hipGraphExec_t exec[2] = {nullptr, nullptr}; unsigned next = 0; size_t total = 0; };
     std::map<GraphKey, GraphPair> graphs;
+    // resident-forward plans per (batch, h, w); like the graphs, dropped
+    // whenever weights, scales or tuned tiles change
+    std::map<std::tuple<int, int, int>, std::shared_ptr<const Plan>> plans;
     std::map<std::string, std::pair<int, int>> tuned;  // conv signature -> (tile, splits)
+    std::string tune_key;                   // device arch, HIP runtime version, tile table (tune-cache file key)
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_vals;  // per-layer mode
     std::map<std::tuple<int, int, int>, std::vector<unsigned char *>> host_place;  // placed forward
     std::mutex mu;
@@ -154,6 +159,7 @@ static void drop_graphs(dn_net *net)
         for (hipGraphExec_t e : kv.second.exec)
             if (e) (void)hipGraphExecDestroy(e);
     net->graphs.clear();
+    net->plans.clear();
 }
 
 // ---------------------------------------------------------------- helpers
@@ -619,6 +625,19 @@ extern "C" dn_status dn_net_create(const dn_layer_desc *layers, int n, const dn_
     net->cw.resize(n);
     net->in_c = chans;
     net->scale.assign(n + 1, 1.0f);
+    {
+        hipDeviceProp_t prop;
+        int rt = 0;
+        char key[320];
+        if (hipGetDeviceProperties(&prop, o->device) != hipSuccess || hipRuntimeGetVersion(&rt) != hipSuccess) {
+            delete net;
+            return fail(DN_EHIP, "device properties");
+        }
+        snprintf(key, sizeof key, "%s|hip%d|tiles%d", prop.gcnArchName, rt, tile_count());
+        net->tune_key = key;
+        for (char &ch : net->tune_key)
+            if (ch == ' ' || ch == '/') ch = '_';
+    }
     if (hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete net;
         return fail(DN_EHIP, "hipStreamCreate failed");
@@ -803,44 +822,80 @@ extern "C" dn_status dn_load_weights(dn_net *net, int layer, const double *w, co
     return DN_OK;
 }
 
+// The resident plan of (batch, h, w), built once and shared until the next
+// change of weights, scales or tuned tiles.
+static dn_status resident_plan(dn_net *net, int batch, int h, int w, std::shared_ptr<const Plan> *out)
+{
+    const auto key = std::make_tuple(batch, h, w);
+    {
+        std::lock_guard<std::mutex> g(net->mu);
+        auto it = net->plans.find(key);
+        if (it != net->plans.end()) {
+            *out = it->second;
+            return DN_OK;
+        }
+    }
+    auto p = std::make_shared<Plan>();
+    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, p.get()));
+    std::lock_guard<std::mutex> g(net->mu);
+    net->plans[key] = p;
+    *out = p;
+    return DN_OK;
+}
+
 static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, const void *x, int batch, int h,
                                   int w, void *y, hipStream_t s)
 {
+    const GraphKey key{batch, h, w, x, y, arena};
+    if (net->o.use_graph) {
+        // a forward captured for these buffers: its plan, weights and scales
+        // are unchanged (any change drops the graphs), so replay it directly
+        hipGraphExec_t exec = nullptr;
+        size_t need = 0;
+        {
+            std::lock_guard<std::mutex> g(net->mu);
+            auto it = net->graphs.find(key);
+            if (it != net->graphs.end()) {
+                exec = it->second.exec[it->second.next++ & 1];
+                need = it->second.total;
+            }
+        }
+        if (exec) {
+            if (arena_bytes < need) return fail(DN_ENOMEM, "arena has %zu bytes, plan needs %zu", arena_bytes, need);
+            HIPCHK(hipGraphLaunch(exec, s));
+            return DN_OK;
+        }
+    }
     STCHK(check_ready(net, true));
     STCHK(check_dims(net, batch, h, w));
     if (!x || !y) return fail(DN_EINVAL, "x/y are NULL");
     if (!arena) return fail(DN_ESTATE, "no arena bound");
-    Plan p;
-    STCHK(make_plan(net, net->o.dtype, DN_MODE_RESIDENT, batch, h, w, &p));
+    std::shared_ptr<const Plan> pp;
+    STCHK(resident_plan(net, batch, h, w, &pp));
+    const Plan &p = *pp;
     if (arena_bytes < p.total) return fail(DN_ENOMEM, "arena has %zu bytes, plan needs %zu", arena_bytes, p.total);
     if (!net->o.use_graph) return enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, s);
-    GraphKey key{batch, h, w, x, y, arena};
-    hipGraphExec_t exec = nullptr;
-    {
-        std::lock_guard<std::mutex> g(net->mu);
-        auto it = net->graphs.find(key);
-        if (it != net->graphs.end()) exec = it->second.exec[it->second.next++ & 1];
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
+    dn_status rc = enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, net->cap_stream);
+    hipError_t e = hipStreamEndCapture(net->cap_stream, &graph);
+    if (rc != DN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
     }
-    if (!exec) {
-        hipGraph_t graph = nullptr;
-        HIPCHK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
-        dn_status rc = enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, net->cap_stream);
-        hipError_t e = hipStreamEndCapture(net->cap_stream, &graph);
-        if (rc != DN_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess) return fail(DN_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        dn_net::GraphPair gp;
-        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphInstantiate(&gp.exec[i], graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            for (hipGraphExec_t x2 : gp.exec)
-                if (x2) (void)hipGraphExecDestroy(x2);
-            return fail(DN_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
-        }
-        exec = gp.exec[0];
-        gp.next = 1;
+    if (e != hipSuccess) return fail(DN_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    dn_net::GraphPair gp;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphInstantiate(&gp.exec[i], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        for (hipGraphExec_t x2 : gp.exec)
+            if (x2) (void)hipGraphExecDestroy(x2);
+        return fail(DN_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = gp.exec[0];
+    gp.next = 1;
+    gp.total = p.total;
+    {
         std::lock_guard<std::mutex> g(net->mu);
         net->graphs[key] = gp;
     }
@@ -1363,27 +1418,71 @@ extern "C" dn_status dn_ga_place(dn_net *net, const dn_ga_params *p, const float
 
 // ---------------------------------------------------------------- autotuner
 
+// $DN_TUNE_CACHE holds lines "<device key>/<conv signature> <tile> <splits>";
+// only lines whose device key is this net's (same GPU architecture, HIP
+// runtime version and tile table) are used, so a cache written elsewhere
+// never selects tiles here.  Lines of other keys are kept when saving.
+static void read_tune_file(const char *path, std::vector<std::pair<std::string, std::pair<int, int>>> *out)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int t, s;
+    while (fscanf(f, "%511s %d %d", key, &t, &s) == 3) out->push_back({key, {t, s}});
+    fclose(f);
+}
+
 static void load_tune_cache(dn_net *net)
 {
     const char *path = getenv("DN_TUNE_CACHE");
     if (!path) return;
-    FILE *f = fopen(path, "r");
-    if (!f) return;
-    char key[256];
-    int t, s;
-    while (fscanf(f, "%255s %d %d", key, &t, &s) == 3)
-        if (((t >= 0 && t < tile_count()) || t == HALO_TILE) && s >= 1) net->tuned[key] = {t, s};
-    fclose(f);
+    std::vector<std::pair<std::string, std::pair<int, int>>> lines;
+    read_tune_file(path, &lines);
+    const std::string pre = net->tune_key + "/";
+    for (auto &l : lines) {
+        if (l.first.compare(0, pre.size(), pre) != 0) continue;
+        const int t = l.second.first, s = l.second.second;
+        if (((t >= 0 && t < tile_count()) || t == HALO_TILE) && s >= 1)
+            net->tuned[l.first.substr(pre.size())] = {t, s};
+    }
 }
 
 static void save_tune_cache(const dn_net *net)
 {
     const char *path = getenv("DN_TUNE_CACHE");
     if (!path) return;
+    std::vector<std::pair<std::string, std::pair<int, int>>> lines;
+    read_tune_file(path, &lines);
+    const std::string pre = net->tune_key + "/";
     FILE *f = fopen(path, "w");
     if (!f) return;
-    for (auto &kv : net->tuned) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    for (auto &l : lines)
+        if (l.first.compare(0, pre.size(), pre) != 0)
+            fprintf(f, "%s %d %d\n", l.first.c_str(), l.second.first, l.second.second);
+    for (auto &kv : net->tuned) fprintf(f, "%s%s %d %d\n", pre.c_str(), kv.first.c_str(), kv.second.first, kv.second.second);
     fclose(f);
+}
+
+// The tuned choice: the fastest candidate, except that candidates within
+// TUNE_TIE of it count as tied and the tie goes to the first in a fixed order
+// (fewest splits, then lowest config index), so that two configurations whose
+// timings differ by run-to-run noise do not trade places between runs.
+constexpr float TUNE_TIE = 0.03f;
+static void pick_tuned(const std::vector<std::tuple<float, int, int>> &timed, int *tile, int *splits)
+{
+    if (timed.empty()) return;
+    float best = 1e30f;
+    for (const auto &c : timed) best = std::min(best, std::get<0>(c));
+    bool have = false;
+    for (const auto &c : timed) {
+        if (std::get<0>(c) > best * (1.0f + TUNE_TIE)) continue;
+        const int t = std::get<1>(c), sp = std::get<2>(c);
+        if (!have || sp < *splits || (sp == *splits && t < *tile)) {
+            *tile = t;
+            *splits = sp;
+            have = true;
+        }
+    }
 }
 
 static bool tile_fits(int tile, int cout_p)
@@ -1418,8 +1517,7 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
         if (net->tuned.count(sig)) continue;
         const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
         const int nkt = net->cw[op.conv].k_pad / bk_el(p.dtype);
-        float best = 1e30f;
-        int bt = op.tile, bs = op.splits;
+        std::vector<std::tuple<float, int, int>> timed;  // (ms, tile, splits)
         std::vector<int> cands;
         if (op_halo_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
         for (int t = 0; t < tile_count(); ++t)
@@ -1445,10 +1543,12 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
                         ms /= iters;
                     }
                 }
-                if (rc == DN_OK && ms < best) { best = ms; bt = t; bs = sp; }
+                if (rc == DN_OK) timed.emplace_back(ms, t, sp);
             }
         }
         if (rc != DN_OK) break;
+        int bt = op.tile, bs = op.splits;
+        pick_tuned(timed, &bt, &bs);
         std::lock_guard<std::mutex> g(net->mu);
         net->tuned[sig] = {bt, bs};
     }
@@ -2393,8 +2493,7 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         if (op_halo_ok(net, dt, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
         for (int t = 0; t < tile_count(); ++t)
             if (tile_fits(t, op.cout_p)) cands.push_back(t);
-        float best = 1e30f;
-        int bt = op.tile, bs = op.splits;
+        std::vector<std::tuple<float, int, int>> timed;
         for (int t : cands) {
             const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
@@ -2404,9 +2503,11 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
                 if (sp > 1 && (size_t)sp * M * op.cout_p * 4 > BWD_TUNE_SCRATCH) continue;
                 float ms = 0.f;
                 STCHK(time_candidate([&] { return enqueue_op(net, p, op, base, s, false, t, sp); }, e0, e1, s, &ms));
-                if (ms < best) { best = ms; bt = t; bs = sp; }
+                timed.emplace_back(ms, t, sp);
             }
         }
+        int bt = op.tile, bs = op.splits;
+        pick_tuned(timed, &bt, &bs);
         std::lock_guard<std::mutex> g(net->mu);
         net->tuned[sig] = {bt, bs};
     }
@@ -2428,8 +2529,7 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         if (halo_ok(dt, a)) cands.push_back(HALO_TILE);
         for (int t = 0; t < tile_count(); ++t)
             if (tile_fits(t, a.cout_p)) cands.push_back(t);
-        float best = 1e30f;
-        std::pair<int, int> bt{-1, 0};
+        std::vector<std::tuple<float, int, int>> timed;
         for (int t : cands) {
             const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((a.M + tc.bm - 1) / tc.bm) * ((a.cout_p + tc.bn - 1) / tc.bn);
@@ -2449,9 +2549,11 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
                     return enqueue_conv_backward(&f, gy, cw.wb, cw.bzero, cw.bscale, b.acc[k], base + b.goff[op.in],
                                                  scratch, BWD_TUNE_SCRATCH, s, t, sp);
                 }, e0, e1, s, &ms));
-                if (ms < best) { best = ms; bt = {t, sp}; }
+                timed.emplace_back(ms, t, sp);
             }
         }
+        std::pair<int, int> bt{-1, 0};
+        pick_tuned(timed, &bt.first, &bt.second);
         std::lock_guard<std::mutex> g(net->mu);
         net->tuned[sig] = bt;
     }

@@ -238,3 +238,39 @@ def test_state_errors(dn):
     with pytest.raises(dn.DnError) as e:
         n.forward(x, 2, 32, 32, y)
     assert e.value.status == dn.DN_EINVAL  # batch above max_batch
+
+
+def test_tune_cache_is_keyed_by_device(dn, tmp_path, monkeypatch):
+    """A tune-cache line is used only under this device's key (GPU architecture,
+    HIP runtime version, tile table): the same line under another
+    architecture's key is ignored, and kept in the file."""
+    torch = G.torch_cuda()
+    net = synth.Net("two", 3, 64, 64, [synth.conv(16, 3), synth.conv(32, 3)])
+    params = synth.make_params(net, 7)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("DN_TUNE_CACHE", str(path))
+
+    def tuned_plan():
+        n = dn.Net(net.layers, 3, 64, 64, 4, dtype=dn.BF16)
+        n.load_params(params)
+        arena = G.empty_bytes(2 * n.arena_bytes(4, 64, 64))
+        n.bind_arena(arena)
+        n.autotune(4, 64, 64)
+        plan = n.layer_plan(1, 4, 64, 64)
+        n.close()
+        return plan
+    tuned_plan()
+    lines = [l.split() for l in path.read_text().splitlines()]
+    assert lines and all("/" in l[0] for l in lines)
+    key = lines[0][0].split("/")[0]
+    assert key.startswith("gfx950") and "|hip" in key and "|tiles" in key, key
+    # this device's key with a split count the tuner never tries (3): used as is
+    path.write_text("".join("%s 0 3\n" % l[0] for l in lines))
+    assert tuned_plan()["splits"] == 3
+    # the same lines under another architecture's key: ignored (tuned afresh), and kept
+    foreign = ["gfx942:sramecc+:xnack-%s 0 3" % l[0][len(key.split("|")[0]):] for l in lines]
+    path.write_text("".join(f + "\n" for f in foreign))
+    assert tuned_plan()["splits"] != 3
+    text = path.read_text()
+    assert all(f in text for f in foreign)
+    torch.cuda.synchronize()
