@@ -20,6 +20,7 @@
 // of a 2x2 pooling window] -> round to the storage type -> NHWC store.
 // Pooling after the activation and after rounding are both exact because the
 // activation and the rounding are monotone non-decreasing.
+#include <algorithm>
 #include <type_traits>
 
 #include "dn_kernels.h"
@@ -806,8 +807,13 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lrow = lane & 15, lgrp = lane >> 4;
-    const int n = blockIdx.z;
-    const int th0 = blockIdx.y * a.th, tw0 = blockIdx.x * FT_W;
+    // tiles in (image, row band, column) order, dealt to the XCDs in
+    // contiguous runs: the halo rows a tile shares with the band above were
+    // read through the same L2 shortly before
+    const int ntx = (a.Wo + FT_W - 1) / FT_W, nty = (a.Ho + a.th - 1) / a.th;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int n = logical / (ntx * nty), trem = logical - n * (ntx * nty);
+    const int th0 = (trem / ntx) * a.th, tw0 = (trem % ntx) * FT_W;
     const int hi0 = th0 * a.stride - a.pad, wi0 = tw0 * a.stride - a.pad;
     const int KS = a.k_pad / KSTEP;
 
@@ -1007,7 +1013,9 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     if (lds > FIRST_LDS_MAX || a.R > FIRST_MAX_R || a.C > 16 || first_cp(a.C) * a.S > 16 || a.cout_p > FIRST_MAX_COUT ||
         a.stride > 2 || (a.cout_p & 3) || (size_t)a.Ho * a.Wo * a.cout_p >= (1u << 31))
         return hipErrorInvalidValue;
-    dim3 grid((a.Wo + FT_W - 1) / FT_W, (a.Ho + b.th - 1) / b.th, a.batch);
+    const long nblk = (long)((a.Wo + FT_W - 1) / FT_W) * ((a.Ho + b.th - 1) / b.th) * a.batch;
+    if (nblk >= (1L << 31)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk);
 #define DN_FIRST_CP(D, P, C, M)                                                                      \
     do {                                                                                             \
         allow_lds(conv_first<D, P, C, M>, lds);                                                      \
@@ -1304,6 +1312,336 @@ hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s)
     }
 }
 
+// ---------------------------------------------------------------- persistent halo kernel
+// The halo kernel's operation and reduction order (every output element is one
+// 16x16 MFMA chain over the same K steps, in order, with the same K subset per
+// lane as the GEMM tiles), restructured so that loads overlap the products:
+//   * two workgroups per CU each loop over TH x 32 output tiles (every
+//     output channel);
+//   * each wave keeps the weights of its output channels (NBP 16-channel
+//     blocks of NG groups) in registers for the whole run (no per-tile weight
+//     staging) and owns a part of each tile's 16-pixel MFMA blocks (NQ parts,
+//     NG * NQ = 4 waves); one fragment read from LDS feeds one MFMA per
+//     channel block;
+//   * a block is 16 consecutive pixels of one output row, so the 16 lanes of
+//     a fragment read hit 16 distinct LDS banks (odd chunk pitch per pixel);
+//     a wave owns blocks in vertical pairs, so with a fused 2x2 pool each
+//     window's four outputs sit in one lane's accumulators (rows r and r+1,
+//     two neighbouring columns);
+//   * input windows travel global -> LDS directly (buffer_load ... lds) into
+//     NBUF buffers, so the windows of the next NBUF-1 tiles are in flight
+//     while one is multiplied (one barrier per tile);
+//   * tiles are dealt out in runs of consecutive tiles per XCD, so the halo
+//     rows and columns that neighbouring tiles share are read through the
+//     same L2.
+
+// Output rows per tile: 16, or 8 for four 16-channel blocks (whose
+// accumulators and weights would not leave room for 16 rows).
+__host__ __device__ constexpr int h2_th(int nb) { return nb >= 4 ? 8 : 16; }
+// K steps whose weights a wave keeps in registers (BF16 / FP32: 10, FP8: 5).
+__host__ __device__ constexpr int h2_ksmax(int dt) { return dt == FP8 ? 5 : 10; }
+constexpr int H2_KSMAX = 10;
+constexpr int H2_MAXBLK = 16;  // 1 KB window blocks one wave transfers per tile (at most)
+
+// Chunk pitch of a window pixel: odd (the 16 lanes of a fragment read, 16
+// consecutive pixels, hit distinct banks) and at least one chunk longer than
+// the pixel's channels (the padding chunk, loaded as zeros, is what K
+// segments past K read).
+__host__ __device__ constexpr int h2_pitch(int cps) { return (cps & 1) ? cps + 2 : cps + 1; }
+// 16-channel blocks per wave: every block up to 3, two of four.
+__host__ __device__ constexpr int h2_nbp(int nb) { return nb == 4 ? 2 : nb; }
+// Tile row of block i of pixel part q (of nq): blocks come as (row pair, row
+// in pair, column half), column half fastest; row pairs are dealt to the
+// parts in turn.
+__device__ __forceinline__ int h2_row(int q, int nq, int i) { return 2 * (q + nq * (i >> 2)) + ((i >> 1) & 1); }
+
+// s_waitcnt vmcnt(n) for a run-time n in [0, 40] (larger n waits for 0).
+template <int N> __device__ __forceinline__ void wait_vm_upto(int n)
+{
+    if constexpr (N > 0) {
+        if (n == N) { wait_vm<N>(); return; }
+        wait_vm_upto<N - 1>(n);
+    } else {
+        wait_vm<0>();
+    }
+}
+
+template <int DT, bool POOL, int NB, bool AM = false>
+__global__ void __launch_bounds__(256, 2) conv_halo2(ConvArgs a, int nbuf)
+{
+    constexpr int ES = esize(DT), SEG = seg_el(DT);
+    constexpr int SPL = Tr<DT>::SPL;
+    constexpr int KPL = SPL * SEG, KSTEP = 4 * KPL;
+    constexpr int KSM = h2_ksmax(DT);
+    constexpr int NBP = h2_nbp(NB), NG = NB / NBP, NQ = 4 / NG;
+    constexpr int TH = h2_th(NB), BLOCKS = TH * HT_W / 16, BPW = BLOCKS / NQ;
+    static_assert(NG * NBP == NB && (TH / 2) % NQ == 0, "wave split");
+    extern __shared__ __align__(16) unsigned char halo_raw[];
+    u32x4 *lds = reinterpret_cast<u32x4 *>(halo_raw);
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wg = wave % NG, wq = wave / NG;  // channel group, pixel part
+    const int lrow = lane & 15, lgrp = lane >> 4;
+    const int K = a.R * a.S * a.cin_p;
+    const int KS = (K + KSTEP - 1) / KSTEP;
+    const int cps = a.cin_p / SEG, pst = h2_pitch(cps);
+    const int LH = (TH - 1) * a.stride + a.R, LW = (HT_W - 1) * a.stride + a.S;
+    const int npx = LH * LW;
+    const int wslots = (npx * pst + 63) / 64 * 64, nblk = wslots / 64;  // 16-byte slots per buffer
+    const int ntw = (a.Wo + HT_W - 1) / HT_W, nth = (a.Ho + TH - 1) / TH;
+    const int per_img = ntw * nth, total = a.batch * per_img;
+    const unsigned img_bytes = (unsigned)((size_t)a.H * a.W * a.cin_p * ES);
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
+
+    // this workgroup's tiles: XCD (blockIdx % 8) owns a run of consecutive tiles
+    const int xcd = blockIdx.x & 7, li = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
+    const int run = (total + 7) / 8;
+    const int t_end = min(total, (xcd + 1) * run);
+    const int t0 = xcd * run + li;
+    if (t0 >= t_end) return;  // whole workgroup
+    const int my_tiles = (t_end - t0 + per_xcd - 1) / per_xcd;
+
+    // window slots this wave transfers: blocks wave, wave + 4, ...; lane L
+    // of a block fills slot 64*block + L = pixel * pst + chunk (chunks past
+    // the pixel's channels are padding and load zeros)
+    const int dw = nblk > wave ? (nblk - wave + 3) / 4 : 0;
+    const FastDiv by_pst(pst), by_lw(LW);
+    int s_lr[H2_MAXBLK], s_lc[H2_MAXBLK], s_off[H2_MAXBLK];
+#pragma unroll
+    for (int q = 0; q < H2_MAXBLK; ++q) {
+        const int sl = (wave + 4 * q) * 64 + lane;
+        const int px = by_pst.div(sl), ch = sl - px * pst;
+        const int lr = by_lw.div(px), lc = px - lr * LW;
+        const bool live = q < dw && ch < cps && px < npx;
+        s_lr[q] = live ? lr : -(1 << 20);
+        s_lc[q] = lc;
+        s_off[q] = (lc * a.cin_p + ch * SEG) * ES;
+    }
+    auto issue = [&](int k) {  // the window of this workgroup's k-th tile into buffer k % nbuf
+        const int tt = t0 + k * per_xcd;
+        const int n = tt / per_img, rem = tt - n * per_img;
+        const int hi0 = (rem / ntw) * TH * a.stride - a.pad, wi0 = (rem % ntw) * HT_W * a.stride - a.pad;
+        i32x4 rs = make_rsrc(reinterpret_cast<const unsigned char *>(a.x) + (size_t)n * img_bytes, img_bytes);
+        // wave-uniform by construction; keep it in scalar registers
+        rs.x = __builtin_amdgcn_readfirstlane(rs.x);
+        rs.y = __builtin_amdgcn_readfirstlane(rs.y);
+        rs.z = __builtin_amdgcn_readfirstlane(rs.z);
+        rs.w = __builtin_amdgcn_readfirstlane(rs.w);
+        u32x4 *dst = lds + (k % nbuf) * wslots;
+#pragma unroll
+        for (int q = 0; q < H2_MAXBLK; ++q) {
+            if (q >= dw) break;  // wave-uniform
+            const int hi = hi0 + s_lr[q], wi = wi0 + s_lc[q];
+            const bool ok = (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+            const unsigned off = ok ? (unsigned)((hi * a.W + wi0) * a.cin_p * ES + s_off[q]) : DN_OOB;
+            dma16(rs, off, dst + (wave + 4 * q) * 64);
+        }
+    };
+    // the first nbuf - 1 windows go out before anything else
+    for (int k = 0; k < nbuf - 1 && k < my_tiles; ++k) issue(k);
+
+    // weights of this wave's output channels, all K steps, in registers
+    u32x4 wr[NBP][KSM][SPL];
+#pragma unroll
+    for (int nb = 0; nb < NBP; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks)
+#pragma unroll
+            for (int j = 0; j < SPL; ++j) {
+                const int ch = (wg * NBP + nb) * 16 + lrow;
+                const int k = ks * KSTEP + lgrp * KPL + j * SEG;
+                wr[nb][ks][j] = (ks < KS && ch < a.cout_p) ? gload16(a.w, ((size_t)ch * a.k_pad + k) * ES) : z4;
+            }
+    // byte offset, relative to the lane's pixel, of the 16-byte chunk that
+    // holds this lane's K segment j of step ks; segments past K read the
+    // pixel's own padding chunk (always zero)
+    int toffb[KSM][SPL];
+#pragma unroll
+    for (int ks = 0; ks < KSM; ++ks)
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            const int k = ks * KSTEP + lgrp * KPL + j * SEG;
+            int o = cps;
+            if (k < K) {
+                const int tap = k / a.cin_p, c0 = k - tap * a.cin_p;
+                const int r = tap / a.S, sx = tap - r * a.S;
+                o = (r * LW + sx) * pst + c0 / SEG;
+            }
+            toffb[ks][j] = o * 16;
+        }
+    // this wave's blocks: block i is tile row h2_row(wq, NQ, i), columns
+    // 16 * (i & 1) + (0..15); lane lrow reads the A row of pixel lrow
+    int pbb[BPW];
+#pragma unroll
+    for (int i = 0; i < BPW; ++i)
+        pbb[i] = (h2_row(wq, NQ, i) * a.stride * LW + (16 * (i & 1) + lrow) * a.stride) * pst * 16;
+    float bias[NBP], scl[NBP];
+#pragma unroll
+    for (int nb = 0; nb < NBP; ++nb) {
+        const int col = (wg * NBP + nb) * 16 + lrow;
+        bias[nb] = col < a.cout_p ? a.bias[col] : 0.0f;
+        scl[nb] = (DT == FP8 && col < a.cout_p) ? a.wscale[col] * a.in_scale : 1.0f;
+    }
+    const int Hp = a.Ho >> 1, Wp = a.Wo >> 1;
+    const size_t img = POOL ? (size_t)Hp * Wp * a.cout_p : (size_t)a.Ho * a.Wo * a.cout_p;
+
+    for (int k = 0; k < my_tiles; ++k) {
+        // this wave's transfers of tile k landed (loads complete in order; the
+        // ones still allowed in flight are those of the tiles issued after it)
+        wait_vm_upto<40>(min(nbuf - 2, my_tiles - 1 - k) * dw);
+        // the barrier: every wave's transfers landed and every wave is done
+        // with tile k - 1's buffer
+        lds_barrier();
+        if (k + nbuf - 1 < my_tiles) issue(k + nbuf - 1);
+        const int t = t0 + k * per_xcd;
+        const int n = t / per_img, rem = t - n * per_img;
+        const int th0 = (rem / ntw) * TH, tw0 = (rem % ntw) * HT_W;
+
+        f4 acc[BPW][NBP];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i)
+#pragma unroll
+            for (int nb = 0; nb < NBP; ++nb) acc[i][nb] = f4{0.f, 0.f, 0.f, 0.f};
+        const unsigned char *wbuf = halo_raw + (size_t)(k % nbuf) * wslots * 16;
+        const unsigned char *blk[BPW];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) blk[i] = wbuf + pbb[i];
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks) {
+            if (ks < KS) {
+                u32x4 af[BPW][SPL];
+#pragma unroll
+                for (int i = 0; i < BPW; ++i)
+#pragma unroll
+                    for (int j = 0; j < SPL; ++j) af[i][j] = *reinterpret_cast<const u32x4 *>(blk[i] + toffb[ks][j]);
+#pragma unroll
+                for (int i = 0; i < BPW; ++i)
+#pragma unroll
+                    for (int nb = 0; nb < NBP; ++nb) mma<DT>(acc[i][nb], af[i], wr[nb][ks]);
+            }
+        }
+
+        // epilogue: bias, activation, [residual], [2x2 max], round, NHWC store
+        unsigned char *yimg = reinterpret_cast<unsigned char *>(a.y) + (size_t)n * img * ES;
+        const unsigned char *rimg = a.res ? reinterpret_cast<const unsigned char *>(a.res) + (size_t)n * img * ES : nullptr;
+#pragma unroll
+        for (int nb = 0; nb < NBP; ++nb) {
+            const int col = (wg * NBP + nb) * 16 + lrow;
+            if (col >= a.cout_p) continue;
+            if constexpr (POOL) {
+                // blocks i (row 2k) and i + 2 (row 2k + 1) of the same column
+                // half: lane column pairs (4*lgrp + 2j, + 1) are the windows
+#pragma unroll
+                for (int i = 0; i < BPW; ++i) {
+                    if (i & 2) continue;
+                    const int hp = (th0 + h2_row(wq, NQ, i)) >> 1;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const float w4[4] = {acc[i][nb][2 * j], acc[i][nb][2 * j + 1], acc[i + 2][nb][2 * j],
+                                             acc[i + 2][nb][2 * j + 1]};
+                        const float mx = fmaxf(fmaxf(w4[0], w4[1]), fmaxf(w4[2], w4[3]));
+                        const float o = activate(mx * scl[nb] + bias[nb], a.act, a.slope) * a.out_inv_scale;
+                        const int wp = ((tw0 + 16 * (i & 1)) >> 1) + 2 * lgrp + j;
+                        if (hp < Hp && wp < Wp) {
+                            store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
+                            if constexpr (AM)
+                                a.argmax[(size_t)n * img + (hp * Wp + wp) * a.cout_p + col] =
+                                    window_argmax<DT>(w4, scl[nb], bias[nb], a.act, a.slope, a.out_inv_scale);
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < BPW; ++i) {
+                    const int ho = th0 + h2_row(wq, NQ, i);
+                    if (ho >= a.Ho) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int wo = tw0 + 16 * (i & 1) + 4 * lgrp + q;
+                        if (wo >= a.Wo) continue;
+                        const int o = (ho * a.Wo + wo) * a.cout_p + col;
+                        float r = activate(acc[i][nb][q] * scl[nb] + bias[nb], a.act, a.slope);
+                        if (rimg) r += load_el<DT>(rimg, o) * a.res_scale;
+                        store_el<DT>(yimg, o, r * a.out_inv_scale);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Window slots (16 bytes) of one LDS buffer of the persistent halo kernel.
+static int halo2_wslots(int dt, const ConvArgs &a)
+{
+    const int cps = a.cin_p / seg_el(dt);
+    const int th = h2_th((a.cout_p + 15) / 16);
+    const int lh = (th - 1) * a.stride + a.R, lw = (HT_W - 1) * a.stride + a.S;
+    return (lh * lw * h2_pitch(cps) + 63) / 64 * 64;
+}
+
+constexpr size_t H2_LDS_MAX = 76 * 1024;  // two workgroups per CU
+
+// Window buffers: as many as fit (up to 4), at least 2.
+static int halo2_nbuf(int dt, const ConvArgs &a)
+{
+    const size_t per = (size_t)halo2_wslots(dt, a) * 16;
+    int nb = 4;
+    while (nb > 2 && nb * per > H2_LDS_MAX) --nb;
+    return nb;
+}
+
+bool halo2_ok(int dt, const ConvArgs &a)
+{
+    const int kstep = dt == FP8 ? 128 : (dt == BF16 ? 32 : 16);
+    const int K = a.R * a.S * a.cin_p;
+    const int ws = halo2_wslots(dt, a);
+    const int nb = (a.cout_p + 15) / 16;
+    return kblock_ch(dt, a.cin_p, a.R * a.S) == a.cin_p && nb <= 4 && nb != 3 && (K + kstep - 1) / kstep <= h2_ksmax(dt) &&
+           a.stride <= 2 && (size_t)a.Ho * a.Wo * a.cout_p < (1u << 31) &&
+           (size_t)a.H * a.W * a.cin_p * esize(dt) < (1u << 31) && ws / 64 <= 4 * H2_MAXBLK &&
+           2 * (size_t)ws * 16 <= H2_LDS_MAX;
+}
+
+template <int DT, bool POOL, bool AM>
+static hipError_t go_halo2(const ConvArgs &a, int grid, int nbuf, size_t lds, hipStream_t s)
+{
+    switch ((a.cout_p + 15) / 16) {
+    case 1: allow_lds(conv_halo2<DT, POOL, 1, AM>, lds); hipLaunchKernelGGL((conv_halo2<DT, POOL, 1, AM>), dim3(grid), dim3(256), lds, s, a, nbuf); break;
+    case 2: allow_lds(conv_halo2<DT, POOL, 2, AM>, lds); hipLaunchKernelGGL((conv_halo2<DT, POOL, 2, AM>), dim3(grid), dim3(256), lds, s, a, nbuf); break;
+    case 4: allow_lds(conv_halo2<DT, POOL, 4, AM>, lds); hipLaunchKernelGGL((conv_halo2<DT, POOL, 4, AM>), dim3(grid), dim3(256), lds, s, a, nbuf); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t go_halo2_dt(const ConvArgs &a, int grid, int nbuf, size_t lds, hipStream_t s)
+{
+    if constexpr (DT != FP8) {
+        if (a.pool && a.argmax) return go_halo2<DT, true, true>(a, grid, nbuf, lds, s);
+    }
+    return a.pool ? go_halo2<DT, true, false>(a, grid, nbuf, lds, s) : go_halo2<DT, false, false>(a, grid, nbuf, lds, s);
+}
+
+hipError_t launch_conv_halo2(int dt, const ConvArgs &a, hipStream_t s)
+{
+    if (!halo2_ok(dt, a)) return hipErrorInvalidValue;
+    const int th = h2_th((a.cout_p + 15) / 16);
+    const long tiles = (long)a.batch * ((a.Ho + th - 1) / th) * ((a.Wo + HT_W - 1) / HT_W);
+    const int nbuf = halo2_nbuf(dt, a);
+    const size_t lds = (size_t)nbuf * halo2_wslots(dt, a) * 16;
+    // two workgroups per CU, a multiple of 8 (the tile runs are per XCD)
+    const long want = std::min<long>(tiles, 512L);
+    const int grid = (int)std::max<long>(8, (want + 7) / 8 * 8);
+    switch (dt) {
+    case F32: return go_halo2_dt<F32>(a, grid, nbuf, lds, s);
+    case BF16: return go_halo2_dt<BF16>(a, grid, nbuf, lds, s);
+    case FP8: return go_halo2_dt<FP8>(a, grid, nbuf, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 static const TileCfg kTiles[] = {
@@ -1448,6 +1786,7 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s)
 {
     if (tile == HALO_TILE) return a.splits > 1 ? hipErrorInvalidValue : launch_conv_halo(dt, a, s);
+    if (tile == HALO2_TILE) return a.splits > 1 ? hipErrorInvalidValue : launch_conv_halo2(dt, a, s);
     switch (dt) {
     case F32: return dispatch<F32>(tile, a, s);
     case BF16: return dispatch<BF16>(tile, a, s);

@@ -90,6 +90,11 @@ size_t first_lds_bytes(int dt, int C, int R, int S, int stride);
 constexpr int HALO_TILE = 100;
 bool halo_ok(int dt, const ConvArgs &a);
 hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s);
+// The persistent halo kernel (weights in registers, double-buffered windows,
+// same reduction order): launch_conv(dt, HALO2_TILE, ...) when halo2_ok().
+constexpr int HALO2_TILE = 101;
+bool halo2_ok(int dt, const ConvArgs &a);
+hipError_t launch_conv_halo2(int dt, const ConvArgs &a, hipStream_t s);
 
 struct TileCfg { int bm, bn, wm, wn, mf; };  // mf: MFMA block side for BF16 (0 = 16)
 

@@ -289,6 +289,20 @@ static bool op_halo_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
     return halo_ok(dtype, a);
 }
 
+// Can this conv op run the persistent halo kernel?
+static bool op_halo2_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
+{
+    if (op.kind != OP_CONV || op.first) return false;
+    const dn_layer_desc &d = net->L[op.conv];
+    ConvArgs a{};
+    a.R = a.S = d.ksize; a.stride = d.stride; a.pad = d.pad;
+    a.cin_p = op.cin_p; a.cout_p = op.cout_p; a.k_pad = k_pad;
+    a.H = op.H; a.W = op.W; a.Ho = op.pool ? op.Ho * 2 : op.Ho; a.Wo = op.pool ? op.Wo * 2 : op.Wo;
+    return halo2_ok(dtype, a);
+}
+
+static bool is_halo(int t) { return t == HALO_TILE || t == HALO2_TILE; }
+
 // pool_fuse_upto >= 0 (input-gradient pass, per-layer mode otherwise): fuse a
 // conv with the 2x2/2 pool after it when that pool's layer index is at most
 // pool_fuse_upto; no residual fusion.
@@ -448,6 +462,9 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         if (it != net->tuned.end()) {
             op.tile = it->second.first;
             op.splits = it->second.second;
+        } else if (op_halo2_ok(net, dtype, op, k_pad)) {
+            op.tile = HALO2_TILE;
+            op.splits = 1;
         } else if (op_halo_ok(net, dtype, op, k_pad)) {
             op.tile = HALO_TILE;
             op.splits = 1;
@@ -1442,7 +1459,7 @@ static void load_tune_cache(dn_net *net)
     for (auto &l : lines) {
         if (l.first.compare(0, pre.size(), pre) != 0) continue;
         const int t = l.second.first, s = l.second.second;
-        if (((t >= 0 && t < tile_count()) || t == HALO_TILE) && s >= 1)
+        if (((t >= 0 && t < tile_count()) || is_halo(t)) && s >= 1)
             net->tuned[l.first.substr(pre.size())] = {t, s};
     }
 }
@@ -1520,14 +1537,15 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
         std::vector<std::tuple<float, int, int>> timed;  // (ms, tile, splits)
         std::vector<int> cands;
         if (op_halo_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
+        if (op_halo2_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO2_TILE);
         for (int t = 0; t < tile_count(); ++t)
             if (tile_fits(t, op.cout_p)) cands.push_back(t);
         for (int t : cands) {
             if (rc != DN_OK) break;
-            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
+            const TileCfg tc = is_halo(t) ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
             for (int sp = 1; sp <= 16 && rc == DN_OK; sp *= 2) {
-                if (t == HALO_TILE && sp > 1) break;
+                if (is_halo(t) && sp > 1) break;
                 if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 const size_t need = sp > 1 ? (size_t)sp * M * op.cout_p * 4 : 0;
                 if (p.ws_off + need > net->arena_bytes) continue;
@@ -1824,14 +1842,16 @@ static dn_status conv_geometry(const dn_conv_desc *d, ConvArgs *a, int *tile, in
     heuristic_tile(M, cout_p, k_pad / bk_el(dt), &ht, &hs);
     if (t < 0) t = ht;
     if (sp <= 0) sp = (d->tile < 0) ? hs : 1;
-    if (t >= tile_count() && t != HALO_TILE) return fail(DN_EINVAL, "tile %d out of range", t);
+    if (t >= tile_count() && !is_halo(t)) return fail(DN_EINVAL, "tile %d out of range", t);
     const int nkt = std::max(1, k_pad / bk_el(dt));
     if (sp > nkt) sp = nkt;
-    if (d->input_nchw || t == HALO_TILE) sp = 1;
-    if (t == HALO_TILE) {
+    if (d->input_nchw || is_halo(t)) sp = 1;
+    if (is_halo(t)) {
         ConvArgs h{};
         h.R = h.S = d->ksize; h.stride = d->stride; h.pad = d->pad; h.cin_p = cin_p; h.cout_p = cout_p; h.k_pad = k_pad;
-        if (!halo_ok(dt, h)) return fail(DN_EUNSUPPORTED, "conv desc: this shape cannot use the halo kernel");
+        h.H = d->in_h; h.W = d->in_w; h.Ho = Ho; h.Wo = Wo;
+        if (t == HALO_TILE ? !halo_ok(dt, h) : !halo2_ok(dt, h))
+            return fail(DN_EUNSUPPORTED, "conv desc: this shape cannot use the halo kernel %d", t);
     }
     if (a) {
         memset(a, 0, sizeof *a);
@@ -2004,8 +2024,11 @@ static dn_status bwd_desc(const dn_conv_desc *f, int accumulate, dn_conv_desc *b
     STCHK(conv_geometry(b, &a, nullptr, nullptr, nullptr, nullptr, nullptr));
     if (tile >= 0) {  // an explicit (tuned) choice
         if (tile == HALO_TILE && !halo_ok(f->dtype, a)) return fail(DN_EUNSUPPORTED, "backward: halo tile does not fit");
+        if (tile == HALO2_TILE && !halo2_ok(f->dtype, a)) return fail(DN_EUNSUPPORTED, "backward: halo tile does not fit");
         b->tile = tile;
-        b->splits = tile == HALO_TILE ? 1 : std::max(1, splits);
+        b->splits = is_halo(tile) ? 1 : std::max(1, splits);
+    } else if (halo2_ok(f->dtype, a)) {
+        b->tile = HALO2_TILE;
     } else if (halo_ok(f->dtype, a)) {
         b->tile = HALO_TILE;
     }
@@ -2491,14 +2514,15 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         const int nkt = net->cw[op.conv].k_pad / bk_el(dt);
         std::vector<int> cands;
         if (op_halo_ok(net, dt, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
+        if (op_halo2_ok(net, dt, op, net->cw[op.conv].k_pad)) cands.push_back(HALO2_TILE);
         for (int t = 0; t < tile_count(); ++t)
             if (tile_fits(t, op.cout_p)) cands.push_back(t);
         std::vector<std::tuple<float, int, int>> timed;
         for (int t : cands) {
-            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
+            const TileCfg tc = is_halo(t) ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
             for (int sp = 1; sp <= 16; sp *= 2) {
-                if (t == HALO_TILE && sp > 1) break;
+                if (is_halo(t) && sp > 1) break;
                 if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 if (sp > 1 && (size_t)sp * M * op.cout_p * 4 > BWD_TUNE_SCRATCH) continue;
                 float ms = 0.f;
@@ -2527,14 +2551,15 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         const int nkt = a.k_pad / bk_el(dt);
         std::vector<int> cands;
         if (halo_ok(dt, a)) cands.push_back(HALO_TILE);
+        if (halo2_ok(dt, a)) cands.push_back(HALO2_TILE);
         for (int t = 0; t < tile_count(); ++t)
             if (tile_fits(t, a.cout_p)) cands.push_back(t);
         std::vector<std::tuple<float, int, int>> timed;
         for (int t : cands) {
-            const TileCfg tc = t == HALO_TILE ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
+            const TileCfg tc = is_halo(t) ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((a.M + tc.bm - 1) / tc.bm) * ((a.cout_p + tc.bn - 1) / tc.bn);
             for (int sp = 1; sp <= 16; sp *= 2) {
-                if (t == HALO_TILE && sp > 1) break;
+                if (is_halo(t) && sp > 1) break;
                 if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 dn_conv_desc cd;
                 int h2, w2, hz2, wz2;

@@ -147,17 +147,25 @@ HALO = [
     (2, 10, 10, 64, 32, 1, 1, 0, 0, 0),   # 1x1 reduction of a residual unit
     (1, 17, 19, 16, 48, 3, 2, 1, 0, 0),   # stride 2, odd sizes
     (2, 12, 14, 16, 32, 3, 1, 1, 0, 1),   # fused residual add
+    (2, 18, 40, 32, 48, 3, 1, 1, 1, 0),   # three 16-channel blocks
 ]
-HALO_TILE = 100
+# full-size 9-layer c2 / c3 classes: more tiles than workgroups, so the
+# persistent kernel runs several tiles per workgroup and per XCD run
+HALO_BIG = [
+    (8, 208, 208, 16, 32, 3, 1, 1, 1, 0),
+    (16, 104, 104, 32, 64, 3, 1, 1, 1, 0),
+]
+HALO_TILE, HALO2_TILE = 100, 101
 
 
+@pytest.mark.parametrize("tile", [HALO_TILE, HALO2_TILE], ids=["halo", "halo2"])
 @pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
-@pytest.mark.parametrize("shape", HALO, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8] + ("_pool" if s[8] else "") + ("_res" if s[9] else ""))
-def test_halo_kernel_parity(dn, dtype, shape):
+@pytest.mark.parametrize("shape", HALO + HALO_BIG, ids=lambda s: "b%d_%dx%d_c%d_co%d_k%d_s%d_p%d" % s[:8] + ("_pool" if s[8] else "") + ("_res" if s[9] else ""))
+def test_halo_kernel_parity(dn, dtype, shape, tile):
     b, h, w, cin, cout, k, st, pad, pool, resid = shape
     try:
         dn.conv_sizes(dn.conv_desc(b, h, w, cin, cout, k, st, pad, 1, 0.1, 2 if pool else 0, resid, dtype,
-                                   tile=HALO_TILE, splits=1))
+                                   tile=tile, splits=1))
     except dn.DnError as e:
         assert e.status == dn.DN_EUNSUPPORTED
         pytest.skip("shape outside the halo kernel's LDS budget for this dtype")
@@ -169,9 +177,9 @@ def test_halo_kernel_parity(dn, dtype, shape):
     kw = {}
     if dtype == dn.FP8:
         kw = dict(in_scale=G.fp8_scale(x), out_scale=G.fp8_scale(ref), res_scale=G.fp8_scale(r) if resid else 1.0)
-    got = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, res=r, tile=HALO_TILE, splits=1, **kw)
+    got = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, res=r, tile=tile, splits=1, **kw)
     err = G.rel_l2(got, ref)
-    print("halo %s %s rel_l2=%.3e" % (G.NAME[dtype], shape, err))
+    print("halo%s %s %s rel_l2=%.3e" % ("" if tile == HALO_TILE else "2", G.NAME[dtype], shape, err))
     assert err < G.GATE[dtype]
     # same reduction order as the GEMM tiles: identical bits
     gem = G.run_conv(dn, dtype, x, p, k, st, pad, 1, pool=pool, res=r, tile=0, splits=1, **kw)
