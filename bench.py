@@ -142,40 +142,80 @@ def cpu_baseline(budget_s: float = 12.0):
             "host_cpus": os.cpu_count(), "cpus_available": affinity}
 
 
-def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print):
+def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
+            sweep=(("bf16_continuous_batching", (4000.0, 8000.0, 16000.0, 32000.0)),
+                   ("f32_plain_batch1", (1000.0, 2000.0, 4000.0, 8000.0)))):
     """Open-loop serving of the mixed-resolution trace: BF16 continuous batching
-    vs the FP32 plain path (batch 1, one stream, arrival order) on the same GPU."""
+    (8 slots, batches padded to powers of two up to 64) vs the FP32 plain path
+    (batch 1, one stream, arrival order) on the same GPU.  Both replay captured
+    graphs on fixed per-slot regions, with tiles tuned for every (batch, size)
+    they form.  Each path reports the device overlap of its batches (event
+    timestamps) and a capacity sweep: offered rate against served rate and
+    p99 latency, and the first rate at which p99 passes 50 ms."""
     import synth
     from paper_1811_03882_amd import serve
     net = synth.plain9()
     params = synth.make_params(net, synth.SEED_PLAIN)
-    trace = synth.serving_trace(n_requests, rate, synth.SEED_SERVING)
-    sizes = trace.sizes
-    pool = {s: [synth.serving_image(1000000 + 8 * j + k, s).astype(np.float32)[0] for k in range(8)]
-            for j, s in enumerate(sizes)}
+    sizes = synth.serving_trace(1, rate, synth.SEED_SERVING).sizes
+    # camera frames arrive in pinned host buffers (8 distinct frames per size)
+    pool = {s: [torch.from_numpy(synth.serving_image(1000000 + 8 * j + k, s).astype(np.float32)[0]).pin_memory()
+                for k in range(8)] for j, s in enumerate(sizes)}
     image_of = lambda r: pool[r.size][r.rid % 8]
+    rates = dict(sweep)
     out = {}
-    for name, dtype, slots, max_batch, bucketed, graph in (("bf16_continuous_batching", dn.BF16, 8, 64, True, False),
-                                                          ("f32_plain_batch1", dn.F32, 1, 1, False, True)):
+    for name, dtype, slots, max_batch, bucketed in (("bf16_continuous_batching", dn.BF16, 8, 64, True),
+                                                    ("f32_plain_batch1", dn.F32, 1, 1, False)):
         log("[bench] serving %s" % name)
-        n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=graph)
+        t_setup = time.perf_counter()
+        n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=True)
         n.load_params(params)
-        budget = (32 << 30) if bucketed else (1 << 30)  # the HBM activation budget of the serving config
-        ex = serve.DnExecutor(n, torch, budget_bytes=budget, n_slots=slots, image_of=image_of,
-                              max_batch=max_batch, max_size=max(sizes), keep_outputs=False)
-        # warm-up: one request per size (graph capture / first launches), not counted
-        serve.Scheduler(ex, ex.pool.numel(), sizes, max_batch=max_batch, bucketed=bucketed,
-                        pad_pow2=bucketed).run([serve.Request(-1 - k, s, 0.0) for k, s in enumerate(sizes)])
+        ex = serve.DnExecutor(n, torch, budget_bytes=0, n_slots=slots, image_of=image_of, max_batch=max_batch,
+                              max_size=max(sizes), keep_outputs=False, fixed_slots=True, sizes=sizes)
+        batches = [1 << k for k in range(max_batch.bit_length()) if (1 << k) <= max_batch]
+        n.bind_arena(ex.pool, ex.region)  # slot 0's region while tuning
+        for S in sizes:
+            for b in batches:
+                n.autotune(b, S, S)
         torch.cuda.synchronize()
-        sch = serve.Scheduler(ex, ex.pool.numel(), sizes, max_batch=max_batch, bucketed=bucketed, pad_pow2=bucketed)
-        st = sch.run(serve.make_requests(trace))
-        d = st.as_dict()
-        d.update({"dtype": {0: "f32", 1: "bf16"}[dtype], "slots": slots, "budget_gb": ex.pool.numel() / 2 ** 30})
-        out[name] = d
+        # warm-up: capture each slot's graph of every (batch, size), not counted
+        for slot in range(slots):
+            for S in sizes:
+                for b in batches:
+                    h = ex.launch(slot, [serve.Request(-1, S, 0.0)], b, S, 0)
+                    h[0].synchronize()
+        t_setup = time.perf_counter() - t_setup
+
+        def run(rate_, count):
+            trace = synth.serving_trace(count, rate_, synth.SEED_SERVING)
+            sch = serve.Scheduler(ex, ex.pool.numel(), sizes, max_batch=max_batch, bucketed=bucketed,
+                                  pad_pow2=bucketed)
+            ex.intervals.clear()
+            ref = torch.cuda.Event(enable_timing=True)
+            ref.record()
+            st = sch.run(serve.make_requests(trace))
+            torch.cuda.synchronize()
+            d = st.as_dict()
+            d.update({"offered_per_s": rate_, "device": serve.device_overlap(ex.intervals, ref)})
+            return d
+        d = run(rate, n_requests)
+        d.update({"dtype": {0: "f32", 1: "bf16"}[dtype], "slots": slots, "graph": True, "tuned": True,
+                  "budget_gb": ex.pool.numel() / 2 ** 30, "setup_s": t_setup})
         log("[bench]   %s" % d)
+        points = []
+        for r in rates.get(name, ()):
+            pt = run(r, int(min(20000, r * 1.5)))
+            points.append({k: pt[k] for k in ("offered_per_s", "images_per_s", "p50_ms", "p99_ms", "mean_batch",
+                                              "max_inflight")} | {"overlap_frac": pt["device"]["overlap_frac"]})
+            log("[bench]   capacity %s" % points[-1])
+            if pt["p99_ms"] > 500.0:
+                break
+        cross = next((p["offered_per_s"] for p in [d] + points if p["p99_ms"] > 50.0), None)
+        d["capacity"] = {"points": points, "first_rate_p99_over_50ms": cross}
+        out[name] = d
         del ex
         n.close()
-    return {"workload": "%d Poisson requests at %.0f req/s, S uniform over %s, 9-layer CNN" % (n_requests, rate, sizes),
+    return {"workload": "%d Poisson requests at %.0f req/s, S uniform over %s, 9-layer CNN; capacity sweep with "
+                        "min(20000, 1.5 s) of requests per rate" % (n_requests, rate, sizes),
             **out}
 
 

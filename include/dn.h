@@ -85,6 +85,13 @@ typedef struct dn_net_opts {
     int use_graph;       /* 1: resident forwards are captured once per
                             (batch, h, w, x, y, arena) into a hipGraph and replayed */
     int device;          /* HIP device ordinal */
+    int batch_invariant; /* 1: every output element is reduced in an order that
+                            does not depend on the batch size, so an image gives
+                            the same bits alone and inside any batch: the
+                            split-K partition of each conv is a function of its
+                            K alone (dn_layer_plan reports it) and only tiles of
+                            16x16 MFMA blocks run; tiles may still differ with
+                            the batch.  0: tiles and splits tuned per batch. */
 } dn_net_opts;
 
 typedef struct dn_net dn_net;

@@ -198,7 +198,9 @@ __device__ __forceinline__ u32x4 gload16(const void *base, size_t byte_off)
 // Epilogue shared by the implicit-GEMM kernels.  MFMA 16x16 output layout:
 // lane holds column (lane & 15) and rows 4*(lane >> 4) + i, i = 0..3; rowb /
 // colb are this lane's first row / column.  With split-K the raw FP32
-// partial sums go to the scratch plane of this split instead.
+// partial sums go to the scratch plane of this split instead; when the last
+// split finishes the tile in the same launch (a.tile_count set) they are
+// device-scope stores, written through to where every XCD reads them.
 // acc[g][f] holds rows rowb + g*RSTR + (0..3) of column colb + f*CSTR (16x16
 // blocks: RSTR = CSTR = 16; 32x32 blocks split into four row quads: RSTR = 8,
 // CSTR = 32).  Every quad starts at a multiple of 4, so with a fused pool it is
@@ -217,7 +219,10 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][F
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int m = rowb + fm * RSTR + i;
-                    if (m < a.M) P[(size_t)m * a.cout_p + col] = acc[fm][fn][i];
+                    if (m >= a.M) continue;
+                    float *q = P + (size_t)m * a.cout_p + col;
+                    if (a.tile_count) __hip_atomic_store(q, acc[fm][fn][i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    else *q = acc[fm][fn][i];
                 }
         }
         return;
@@ -256,6 +261,126 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f4 (&acc)[FM][F
                 }
             }
         }
+    }
+}
+
+// 16-byte device-scope load (the buffer instruction's SC1 bit): it misses in
+// the caches that other XCDs' stores do not reach.  off: bytes from base.
+__device__ __forceinline__ f4 load16_dev(const float *base, unsigned off)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 16));
+}
+
+// Split-K finish of one output group: rows (2x2 windows when pooled) `ro`,
+// channels col..col+3 (cout_p is a multiple of 4): the partial sums added in
+// split order, then the same epilogue as the unsplit path, one vector store.
+// Both finishes below call it, so they round alike.  The separate finish
+// reads each split's partials with one 16-byte load as it adds them; the
+// in-kernel finish (DEV) issues the device-scope loads of all splits first,
+// so that they are in flight together, then adds them in the same order.
+template <int DT, bool DEV = false> __device__ __forceinline__ void splitk_finish4(const ConvArgs &a, size_t ro, int col)
+{
+    float bias[4], scl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        bias[j] = a.bias[col + j];
+        scl[j] = (DT == FP8) ? a.wscale[col + j] * a.in_scale : 1.0f;
+    }
+    const size_t plane = (size_t)a.M * a.cout_p;
+    auto total = [&](size_t m, float *t) {
+        t[0] = t[1] = t[2] = t[3] = 0.0f;
+        if constexpr (DEV) {
+            f4 v[SPLITK_FUSED_MAX];
+#pragma unroll
+            for (int z = 0; z < SPLITK_FUSED_MAX; ++z)
+                if (z < a.splits) v[z] = load16_dev(a.partial, (unsigned)((z * plane + m * a.cout_p + col) * sizeof(float)));
+#pragma unroll
+            for (int z = 0; z < SPLITK_FUSED_MAX; ++z)
+                if (z < a.splits) { t[0] += v[z][0]; t[1] += v[z][1]; t[2] += v[z][2]; t[3] += v[z][3]; }
+        } else {
+            for (int z = 0; z < a.splits; ++z) {
+                const float4 p = *reinterpret_cast<const float4 *>(a.partial + z * plane + m * a.cout_p + col);
+                t[0] += p.x; t[1] += p.y; t[2] += p.z; t[3] += p.w;
+            }
+        }
+    };
+    float o[4], t[4];
+    if (a.pool) {
+        float w4[4][4];  // [column][window element]
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = -INFINITY;
+        for (int q = 0; q < 4; ++q) {
+            total(ro * 4 + q, t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                w4[j][q] = t[j];
+                o[j] = fmaxf(o[j], activate(t[j] * scl[j] + bias[j], a.act, a.slope));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
+        if (a.argmax) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a.argmax[ro * a.cout_p + col + j] = window_argmax<DT>(w4[j], scl[j], bias[j], a.act, a.slope, a.out_inv_scale);
+        }
+    } else {
+        total(ro, t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = activate(t[j] * scl[j] + bias[j], a.act, a.slope);
+        if (a.res) {
+            float r[4];
+            load4<DT>(a.res, ro * a.cout_p + col, r);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] += r[j] * a.res_scale;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
+    }
+    store4<DT>(a.y, ro * a.cout_p + col, o);
+}
+
+// Separate split-K finish: one thread per output group.
+template <int DT>
+__global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
+{
+    const size_t rows = a.pool ? (size_t)(a.M >> 2) : (size_t)a.M;
+    const int cq = a.cout_p >> 2;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cq) return;
+    splitk_finish4<DT>(a, idx / cq, (int)(idx % cq) * 4);
+}
+
+// In-kernel split-K finish (a.tile_count set).  Each split's workgroup of an
+// output tile, once its partial plane is written, counts itself in the tile's
+// counter; the last of the a.splits workgroups to arrive sums the tile's
+// partials in split order and runs the epilogue, then sets the counter back
+// to zero for the next launch that uses it.  The L2 caches of the XCDs are
+// not coherent with each other: the partials travel by device-scope stores,
+// all complete (vmcnt 0) before the workgroup counts itself, and device-scope
+// loads issued after the count is seen, so no cache-wide write-back or
+// invalidate is needed.
+template <int DT, int BM, int BN, int NT>
+__device__ __forceinline__ void splitk_tail(const ConvArgs &a, int m0, int n0)
+{
+    __shared__ int s_last;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *cnt = a.tile_count + blockIdx.x;
+        const int last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)(a.splits - 1);
+        if (last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = last;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    const int rows = a.pool ? BM / 4 : BM;
+    const int r0 = a.pool ? m0 / 4 : m0;
+    const int rend = a.pool ? a.M / 4 : a.M;
+    constexpr int CQ = BN / 4;
+    for (int i = threadIdx.x; i < rows * CQ; i += NT) {
+        const int r = r0 + i / CQ, col = n0 + (i % CQ) * 4;
+        if (r < rend && col < a.cout_p) splitk_finish4<DT, true>(a, (size_t)r, col);
     }
 }
 
@@ -415,6 +540,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 #undef DN_SSTORE
 
     conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
+    if (a.splits > 1 && a.tile_count) splitk_tail<DT, BM, BN, NT>(a, m0, n0);
 }
 
 // ---------------------------------------------------------------- LDS-DMA variant
@@ -672,67 +798,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     } else {
         conv_epilogue<DT, FM, FN>(a, acc, m0 + wm * WTM + 4 * lgrp, n0 + wn * WTN + lrow);
     }
-}
-
-// Split-K finish: sum the partials in split order, then the same epilogue.
-// One thread per four consecutive output channels (cout_p is a multiple of 4):
-// 16-byte partial loads, one vector store.
-template <int DT>
-__global__ void __launch_bounds__(256) splitk_reduce(ConvArgs a)
-{
-    const size_t rows = a.pool ? (size_t)(a.M >> 2) : (size_t)a.M;
-    const int cq = a.cout_p >> 2;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cq) return;
-    const int col = (int)(idx % cq) * 4;
-    const size_t ro = idx / cq;
-    float bias[4], scl[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        bias[j] = a.bias[col + j];
-        scl[j] = (DT == FP8) ? a.wscale[col + j] * a.in_scale : 1.0f;
-    }
-    const size_t plane = (size_t)a.M * a.cout_p;
-    auto total = [&](size_t m, float *t) {
-        t[0] = t[1] = t[2] = t[3] = 0.0f;
-        for (int z = 0; z < a.splits; ++z) {
-            const float4 p = *reinterpret_cast<const float4 *>(a.partial + z * plane + m * a.cout_p + col);
-            t[0] += p.x; t[1] += p.y; t[2] += p.z; t[3] += p.w;
-        }
-    };
-    float o[4], t[4];
-    if (a.pool) {
-        float w4[4][4];  // [column][window element]
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] = -INFINITY;
-        for (int q = 0; q < 4; ++q) {
-            total(ro * 4 + q, t);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                w4[j][q] = t[j];
-                o[j] = fmaxf(o[j], activate(t[j] * scl[j] + bias[j], a.act, a.slope));
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
-        if (a.argmax) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) a.argmax[ro * a.cout_p + col + j] = window_argmax<DT>(w4[j], scl[j], bias[j], a.act, a.slope, a.out_inv_scale);
-        }
-    } else {
-        total(ro, t);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] = activate(t[j] * scl[j] + bias[j], a.act, a.slope);
-        if (a.res) {
-            float r[4];
-            load4<DT>(a.res, ro * a.cout_p + col, r);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) o[j] += r[j] * a.res_scale;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] *= a.out_inv_scale;
-    }
-    store4<DT>(a.y, ro * a.cout_p + col, o);
+    if (a.splits > 1 && a.tile_count) splitk_tail<DT, BM, BN, 64 * NW>(a, m0, n0);
 }
 
 // Dynamic LDS above the default per-kernel limit must be enabled per kernel.
@@ -1340,7 +1406,6 @@ hipError_t launch_conv_halo(int dt, const ConvArgs &a, hipStream_t s)
 __host__ __device__ constexpr int h2_th(int nb) { return nb >= 4 ? 8 : 16; }
 // K steps whose weights a wave keeps in registers (BF16 / FP32: 10, FP8: 5).
 __host__ __device__ constexpr int h2_ksmax(int dt) { return dt == FP8 ? 5 : 10; }
-constexpr int H2_KSMAX = 10;
 constexpr int H2_MAXBLK = 16;  // 1 KB window blocks one wave transfers per tile (at most)
 
 // Chunk pitch of a window pixel: odd (the 16 lanes of a fragment read, 16
@@ -1700,6 +1765,16 @@ static const TileCfg kTiles[] = {
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 TileCfg tile_cfg(int i) { return kTiles[i]; }
 
+size_t splitk_counters(int M, int cout_p)
+{
+    size_t most = 0;
+    for (int i = 0; i < tile_count(); ++i) {
+        const TileCfg t = kTiles[i];
+        most = std::max(most, (size_t)((M + t.bm - 1) / t.bm) * ((cout_p + t.bn - 1) / t.bn));
+    }
+    return most;
+}
+
 template <int DT, int BM, int BN, int WM, int WN>
 static hipError_t go(const ConvArgs &a, hipStream_t s)
 {
@@ -1785,6 +1860,9 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
 
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s)
 {
+    if (a.tile_count && (a.splits > SPLITK_FUSED_MAX ||
+                         (size_t)a.splits * a.M * a.cout_p * sizeof(float) > 0x7fffffffu))
+        return hipErrorInvalidValue;  // beyond the in-kernel finish's loads
     if (tile == HALO_TILE) return a.splits > 1 ? hipErrorInvalidValue : launch_conv_halo(dt, a, s);
     if (tile == HALO2_TILE) return a.splits > 1 ? hipErrorInvalidValue : launch_conv_halo2(dt, a, s);
     switch (dt) {

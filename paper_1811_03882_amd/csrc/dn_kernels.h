@@ -56,6 +56,10 @@ struct ConvArgs {
     // fused pool only, may be nullptr: per pooled output element, the index
     // 2*dy + dx of the first maximal stored value of its 2x2 window
     unsigned char *argmax;
+    // split-K only, may be nullptr: one zeroed counter per output tile
+    // (splitk_counters()); set, the last split to finish a tile runs the
+    // split-K finish itself, else launch_splitk_reduce must follow
+    unsigned *tile_count;
 };
 
 // First convolution of a network, reading the NCHW FP32 input directly.
@@ -100,10 +104,17 @@ struct TileCfg { int bm, bn, wm, wn, mf; };  // mf: MFMA block side for BF16 (0 
 
 int tile_count();
 TileCfg tile_cfg(int i);
-// Launch the conv (one GEMM launch; for splits > 1 it writes partials and
-// launch_splitk_reduce finishes the epilogue).
+// Launch the conv (one GEMM launch; for splits > 1 it writes partials, and
+// either the last split of each tile (tile_count set) or launch_splitk_reduce
+// finishes the epilogue).
 hipError_t launch_conv(int dt, int tile, const ConvArgs &a, hipStream_t s);
 hipError_t launch_splitk_reduce(int dt, const ConvArgs &a, hipStream_t s);
+// Most splits, and most partial bytes (offsets of its 16-byte loads), of a
+// conv finishing in-kernel (ConvArgs::tile_count set).
+constexpr int SPLITK_FUSED_MAX = 8;
+// Counters ConvArgs::tile_count needs for an M x cout_p GEMM under any tile
+// configuration (the most output tiles any of them makes).
+size_t splitk_counters(int M, int cout_p);
 
 // mode 0 packs k = (cb*R*S + r*S + s)*CB + ci; mode 1 packs k = r*16 + s*first_cp(cin) + c
 // (first-layer kernel; cin_p unused); mode 2 packs the transposed, flipped

@@ -114,6 +114,11 @@ struct Plan {
     std::vector<Op> ops;
     std::vector<Value> vals;   // index = value id
     size_t ws_off = 0, ws_bytes = 0;
+    // split-K tile counters (in-kernel finish), zeroed at the start of every
+    // forward that has a conv finishing in-kernel; 0 bytes = every split conv
+    // finishes with a separate launch
+    size_t cnt_off = 0, cnt_bytes = 0;
+    bool any_fused = false;
     size_t xin_off = 0, yout_off = 0;  // per-layer mode FP32 staging of x / y
     size_t total = 0;
     int out_val = 0;
@@ -231,12 +236,43 @@ static void heuristic_tile(int M, int N, int K, int *tile, int *splits)
     *splits = s;
 }
 
-static std::string conv_sig(int dt, const Op &op, int batch, int R, int stride)
+// Tune-cache signature of a forward conv; batch-invariant nets keep their
+// own entries (their candidates are restricted, see below).
+static std::string conv_sig(int dt, const Op &op, int batch, int R, int stride, bool inv)
 {
     char b[256];
-    snprintf(b, sizeof b, "dt%d_b%d_H%d_W%d_ci%d_co%d_R%d_s%d_p%d_r%d", dt, batch, op.H, op.W, op.cin_p,
-             op.cout_p, R, stride, (int)op.pool, (int)op.res);
+    snprintf(b, sizeof b, "dt%d_b%d_H%d_W%d_ci%d_co%d_R%d_s%d_p%d_r%d%s", dt, batch, op.H, op.W, op.cin_p,
+             op.cout_p, R, stride, (int)op.pool, (int)op.res, inv ? "_bi" : "");
     return b;
+}
+
+static bool is_halo(int t) { return t == HALO_TILE || t == HALO2_TILE; }
+
+// Batch-invariant nets.  An output's sum runs over K in the same order at
+// every batch size when (1) its split-K partition depends on K alone and
+// (2) every tile forms its K-steps from the same MFMA instruction.  (1): one
+// split per 64 K-tiles, at most 4, a power of two (a batch-1 forward of the
+// widest convs still spreads over more workgroups).  (2): tiles of 16x16
+// blocks only; BF16's 32x32 blocks take their products in other groups.  The
+// halo kernels sum in the order of the 16x16 GEMM tiles and run unsplit.
+static int invariant_splits(int nkt)
+{
+    int s = 1;
+    while (s < 4 && nkt >= 64 * s) s *= 2;
+    return s;
+}
+
+static bool invariant_tile_ok(int dt, int tile, int splits)
+{
+    if (is_halo(tile)) return splits == 1;
+    return tile >= 0 && tile < tile_count() && (dt != BF16 || tile_cfg(tile).mf != 32);
+}
+
+// Which split convs finish in the GEMM launch itself (the last workgroup of
+// each output tile to arrive reduces that tile's partial sums).
+static bool finish_in_kernel(int tile, int splits)
+{
+    return splits >= 2 && splits <= SPLITK_FUSED_MAX && !is_halo(tile) && tile >= 0 && tile < tile_count();
 }
 
 // Fill ConvArgs for an op of plan p, reading from base (arena).
@@ -273,6 +309,10 @@ static ConvArgs conv_args(const dn_net *net, const Plan &p, const Op &op, char *
     a.splits = op.splits;
     const int nkt = a.k_pad / bk_el(use32 ? (int)F32 : p.dtype);
     a.ktiles_per_split = (nkt + op.splits - 1) / op.splits;
+    a.tile_count = nullptr;
+    if (p.cnt_bytes && finish_in_kernel(op.tile, op.splits) &&
+        (size_t)op.splits * a.M * a.cout_p * sizeof(float) <= 0x7fffffffu)
+        a.tile_count = (unsigned *)(base + p.cnt_off);
     return a;
 }
 
@@ -300,8 +340,6 @@ static bool op_halo2_ok(const dn_net *net, int dtype, const Op &op, int k_pad)
     a.H = op.H; a.W = op.W; a.Ho = op.pool ? op.Ho * 2 : op.Ho; a.Wo = op.pool ? op.Wo * 2 : op.Wo;
     return halo2_ok(dtype, a);
 }
-
-static bool is_halo(int t) { return t == HALO_TILE || t == HALO2_TILE; }
 
 // pool_fuse_upto >= 0 (input-gradient pass, per-layer mode otherwise): fuse a
 // conv with the 2x2/2 pool after it when that pool's layer index is at most
@@ -450,14 +488,15 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         }
     }
     // split-K scratch and tile choice
-    size_t ws = 0;
+    size_t ws = 0, counters = 0;
     for (Op &op : p.ops) {
         if (op.kind != OP_CONV || op.first) continue;
         const dn_layer_desc &d = net->L[op.conv];
         const int K = d.ksize * d.ksize * op.cin_p;
         const int k_pad = (K + bk_el(dtype) - 1) / bk_el(dtype) * bk_el(dtype);
         const int M = op.pool ? batch * (2 * op.Ho) * (2 * op.Wo) : batch * op.Ho * op.Wo;
-        const std::string sig = conv_sig(dtype, op, batch, d.ksize, d.stride);
+        const bool inv = net->o.batch_invariant != 0;
+        const std::string sig = conv_sig(dtype, op, batch, d.ksize, d.stride, inv);
         auto it = net->tuned.find(sig);
         if (it != net->tuned.end()) {
             op.tile = it->second.first;
@@ -471,10 +510,21 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
         } else {
             heuristic_tile(M, op.cout_p, k_pad / bk_el(dtype), &op.tile, &op.splits);
         }
+        if (inv) {
+            op.splits = invariant_splits(k_pad / bk_el(dtype));
+            if (!invariant_tile_ok(dtype, op.tile, op.splits)) {
+                int unused;
+                heuristic_tile(M, op.cout_p, k_pad / bk_el(dtype), &op.tile, &unused);  // 16x16-block tiles
+            }
+        }
         op.ws_bytes = op.splits > 1 ? align256((size_t)op.splits * M * op.cout_p * 4) : 0;
         ws = std::max(ws, op.ws_bytes);
+        counters = std::max(counters, splitk_counters(M, op.cout_p));  // the autotuner may split any of them
+        p.any_fused = p.any_fused || finish_in_kernel(op.tile, op.splits);
     }
-    p.ws_off = align256(top);
+    p.cnt_off = align256(top);
+    p.cnt_bytes = align256(counters * sizeof(unsigned));
+    p.ws_off = align256(p.cnt_off + p.cnt_bytes);
     p.ws_bytes = ws;
     size_t end = p.ws_off + ws;
     if (mode == DN_MODE_PER_LAYER || gene) {
@@ -536,7 +586,7 @@ static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char
         ConvArgs a = conv_args(net, p, o2, base, use32);
         const int dt = use32 ? F32 : p.dtype;
         HIPCHK(launch_conv(dt, o2.tile, a, s));
-        if (o2.splits > 1) HIPCHK(launch_splitk_reduce(dt, a, s));
+        if (o2.splits > 1 && !a.tile_count) HIPCHK(launch_splitk_reduce(dt, a, s));
     } else if (op.kind == OP_POOL) {
         const dn_layer_desc &d = net->L[op.layer];
         const Value &vi = p.vals[op.in];
@@ -554,8 +604,18 @@ static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char
     return DN_OK;
 }
 
+// Zero the split-K tile counters of plan p (a fill kernel, so that it can be
+// captured in a graph).  Every launch leaves them zero again, so one fill per
+// forward covers all of its split convs.
+static dn_status zero_counters(const Plan &p, char *base, hipStream_t s)
+{
+    if (p.cnt_bytes) HIPCHK(launch_zero_f32((float *)(base + p.cnt_off), p.cnt_bytes / sizeof(float), s));
+    return DN_OK;
+}
+
 static dn_status enqueue_resident(const dn_net *net, const Plan &p, char *base, const float *x, float *y, hipStream_t s)
 {
+    if (p.any_fused) STCHK(zero_counters(p, base, s));
     const Value &v0 = p.vals[0];
     const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
     if (!p.ops[0].first)
@@ -962,6 +1022,7 @@ static dn_status forward_per_layer(dn_net *net, const void *x, int batch, int h,
         HIPCHK(hipMemcpyAsync((*hv)[0], base + v0.off, v0.bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
+    if (p.any_fused) STCHK(zero_counters(p, base, s));
     for (const Op &op : p.ops) {
         if (op.first)
             HIPCHK(hipMemcpyAsync(base + p.xin_off, x, xbytes, hipMemcpyHostToDevice, s));
@@ -1027,6 +1088,7 @@ extern "C" dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h,
     dn_status rc = DN_OK;
     auto run = [&]() -> dn_status {
         HIPCHK(launch_zero_f32(amax, nv, s));
+        if (p.any_fused) STCHK(zero_counters(p, base, s));
         const Value &v0 = p.vals[0];
         if (!p.ops[0].first) HIPCHK(launch_ingest(F32, x, batch, v0.c, h, w, v0.cp, 1.0f, base + v0.off, s));
         HIPCHK(launch_amax(x, (size_t)batch * v0.c * h * w, amax, s));
@@ -1231,6 +1293,7 @@ static dn_status forward_placed(dn_net *net, const unsigned char *gene, const fl
     } else {
         dncpu::ingest(x, batch, v0.c, h, w, v0.cp, (float *)(*hv)[0]);
     }
+    if (p.any_fused) STCHK(zero_counters(p, base, s));
     bool pending = false;  // device->host copies not waited for yet
     for (const Op &op : p.ops) {
         if (op_on_gpu(op, gene)) {
@@ -1526,11 +1589,13 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     char *base = (char *)net->arena;
-    dn_status rc = DN_OK;
+    dn_status rc = zero_counters(p, base, s);
     for (const Op &op : p.ops) {
+        if (rc != DN_OK) break;
         if (op.kind != OP_CONV || op.first) continue;
         const dn_layer_desc &d = net->L[op.conv];
-        const std::string sig = conv_sig(p.dtype, op, batch, d.ksize, d.stride);
+        const bool inv = net->o.batch_invariant != 0;
+        const std::string sig = conv_sig(p.dtype, op, batch, d.ksize, d.stride, inv);
         if (net->tuned.count(sig)) continue;
         const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
         const int nkt = net->cw[op.conv].k_pad / bk_el(p.dtype);
@@ -1544,9 +1609,11 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
             if (rc != DN_OK) break;
             const TileCfg tc = is_halo(t) ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
-            for (int sp = 1; sp <= 16 && rc == DN_OK; sp *= 2) {
+            const int sp_lo = inv ? invariant_splits(nkt) : 1, sp_hi = inv ? sp_lo : 16;
+            for (int sp = sp_lo; sp <= sp_hi && rc == DN_OK; sp *= 2) {
+                if (inv && !invariant_tile_ok(p.dtype, t, sp)) break;
                 if (is_halo(t) && sp > 1) break;
-                if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
+                if (!inv && sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 const size_t need = sp > 1 ? (size_t)sp * M * op.cout_p * 4 : 0;
                 if (p.ws_off + need > net->arena_bytes) continue;
                 float ms = 0.f;
@@ -1789,8 +1856,8 @@ extern "C" dn_status dn_time_layer(dn_net *net, int layer, int batch, int h, int
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    dn_status rc = DN_OK;
-    if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event record");
+    dn_status rc = finish_in_kernel(found->tile, found->splits) ? zero_counters(p, (char *)net->arena, s) : DN_OK;
+    if (rc == DN_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event record");
     for (int i = 0; i < iters && rc == DN_OK; ++i) rc = enqueue_op(net, p, *found, (char *)net->arena, s, false, -1, 0, xin);
     if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
         rc = fail(DN_EHIP, "timed launches failed");
@@ -2190,6 +2257,8 @@ static dn_status make_bwd_plan(const dn_net *net, int target, int batch, int h, 
     BwdPlan b;
     STCHK(make_plan(net, dt, DN_MODE_PER_LAYER, batch, h, w, &b.p, target));
     Plan &p = b.p;
+    p.cnt_bytes = 0;  // regions laid out below; split convs finish with a separate launch
+    p.any_fused = false;
     b.nops = 0;  // ops computing layers 0..target (a conv with its fused pool is one op)
     while (b.nops < (int)p.ops.size() && p.ops[b.nops].layer <= target) ++b.nops;
     b.seed = target + 1;
@@ -2508,7 +2577,8 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         const Op &op = p.ops[k];
         if (op.kind != OP_CONV || op.first) continue;
         const dn_layer_desc &d = net->L[op.conv];
-        const std::string sig = conv_sig(dt, op, batch, d.ksize, d.stride);
+        const bool inv = net->o.batch_invariant != 0;
+        const std::string sig = conv_sig(dt, op, batch, d.ksize, d.stride, inv);
         if (net->tuned.count(sig)) continue;
         const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
         const int nkt = net->cw[op.conv].k_pad / bk_el(dt);
@@ -2521,9 +2591,11 @@ static dn_status autotune_backward(dn_net *net, int layer, int batch, int h, int
         for (int t : cands) {
             const TileCfg tc = is_halo(t) ? TileCfg{1 << 30, 1 << 30, 1, 1} : tile_cfg(t);
             const long tiles = (long)((M + tc.bm - 1) / tc.bm) * ((op.cout_p + tc.bn - 1) / tc.bn);
-            for (int sp = 1; sp <= 16; sp *= 2) {
+            const int sp_lo = inv ? invariant_splits(nkt) : 1, sp_hi = inv ? sp_lo : 16;
+            for (int sp = sp_lo; sp <= sp_hi; sp *= 2) {
+                if (inv && !invariant_tile_ok(dt, t, sp)) break;
                 if (is_halo(t) && sp > 1) break;
-                if (sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
+                if (!inv && sp > 1 && (tiles * sp > 4 * 256 || nkt / sp < 2)) break;
                 if (sp > 1 && (size_t)sp * M * op.cout_p * 4 > BWD_TUNE_SCRATCH) continue;
                 float ms = 0.f;
                 STCHK(time_candidate([&] { return enqueue_op(net, p, op, base, s, false, t, sp); }, e0, e1, s, &ms));

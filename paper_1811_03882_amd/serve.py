@@ -12,6 +12,14 @@ others are in flight are admitted as soon as a slot and budget free up.
 Completion is detected by polling a per-batch event (no blocking sync), which
 frees the slot and the budget and stamps every request's completion time.
 
+With ``fixed_slots`` each slot owns one region of the pool sized for the
+largest batch of the largest bucket, so a (slot, batch, size) always runs on
+the same addresses and the library replays the forward's captured graph (with
+the tiles the autotuner chose for that batch and size) instead of launching
+its kernels one by one; the budget is then the slots' regions.  Each batch's
+device interval (events at its first and last command) is kept, so that the
+overlap of batches on the GPU can be measured (``device_overlap``).
+
 Weights are resident (loaded once), activations live in arenas carved from
 one pre-allocated device pool, and each image crosses PCIe once in and its
 output once out (the placement of Sec. 3.2 of the paper applied per frame).
@@ -319,20 +327,32 @@ class DnExecutor(Executor):
 
     Device memory: one pool of ``budget_bytes`` allocated up front; every batch
     gets a contiguous region [arena | input NCHW FP32 | output NCHW FP32]
-    carved by the scheduler's allocator.  Host images come from ``image_of``
-    (request -> float32 [3, S, S]); they are copied into a per-slot pinned
-    staging buffer and sent with one H2D copy per batch.
+    carved by the scheduler's allocator.  With ``fixed_slots`` the pool is
+    instead n_slots regions of ``slot_bytes()`` (budget_bytes is ignored), and
+    a batch always runs at the start of its slot's region, so its addresses
+    repeat and the net's captured graph for (batch, size) on that slot is
+    replayed.  Host images come from ``image_of`` (request -> float32
+    [3, S, S], numpy or a pinned torch tensor): numpy images are copied into
+    a per-slot pinned staging buffer and sent with one H2D copy per batch,
+    pinned tensors with one H2D copy each.
     """
 
     def __init__(self, net, torch, budget_bytes: int, n_slots: int, image_of: Callable[[Request], np.ndarray],
-                 max_batch: int, max_size: int, keep_outputs: bool = True):
+                 max_batch: int, max_size: int, keep_outputs: bool = True, fixed_slots: bool = False,
+                 sizes: Sequence[int] = ()):
         self.net = net
         self.torch = torch
         self.n_slots = n_slots
         self.image_of = image_of
         self.keep = keep_outputs
+        self.fixed = fixed_slots
+        self._layout = {}
+        if fixed_slots:
+            self.region = max(self._bytes(max_batch, s) for s in (sizes or (max_size,)))
+            budget_bytes = self.region * n_slots
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device="cuda")
         self.base = self.pool.data_ptr()
+        self.intervals = []  # (start event, end event, padded batch) of every launched batch
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         c = net.in_c
         self.stage_in = [torch.empty((max_batch, c, max_size, max_size), dtype=torch.float32).pin_memory()
@@ -340,7 +360,6 @@ class DnExecutor(Executor):
         oc, oh, ow = net.output_shape(max_size, max_size)
         self.stage_out = [torch.empty((max_batch * oc * oh * ow,), dtype=torch.float32).pin_memory()
                           for _ in range(n_slots)]
-        self._layout = {}
 
     def _regions(self, batch: int, size: int):
         key = (batch, size)
@@ -354,21 +373,32 @@ class DnExecutor(Executor):
             self._layout[key] = (ab, xb, yb, (oc, oh, ow))
         return self._layout[key]
 
-    def batch_bytes(self, batch: int, size: int) -> int:
+    def _bytes(self, batch: int, size: int) -> int:
         ab, xb, yb, _ = self._regions(batch, size)
-        return ab + xb + yb
+        return (ab + xb + yb + 255) // 256 * 256
+
+    def batch_bytes(self, batch: int, size: int) -> int:
+        # a fixed slot's whole region: the allocator then hands out whole regions
+        return self.region if self.fixed else self._bytes(batch, size)
 
     def launch(self, slot, reqs, padded, size, offset):
         torch = self.torch
         ab, xb, yb, oshape = self._regions(padded, size)
         s = self.streams[slot]
-        st = self.stage_in[slot]
         c = self.net.in_c
-        hx = st.view(-1)[: padded * c * size * size].view(padded, c, size, size)
-        for j, r in enumerate(reqs):
-            hx[j].copy_(torch.from_numpy(self.image_of(r)))
-        if padded > len(reqs):
-            hx[len(reqs):].zero_()
+        imgs = [self.image_of(r) for r in reqs]
+        # images already in pinned host memory (a capture pipeline's frame
+        # buffers) go to the device one copy each; others are gathered into
+        # the slot's pinned staging buffer first and sent with one copy
+        direct = all(isinstance(im, torch.Tensor) and im.is_pinned() for im in imgs)
+        if not direct:
+            hx = self.stage_in[slot].view(-1)[: padded * c * size * size].view(padded, c, size, size)
+            for j, im in enumerate(imgs):
+                hx[j].copy_(torch.from_numpy(im))
+            if padded > len(imgs):
+                hx[len(imgs):].zero_()
+        if self.fixed:
+            offset = slot * self.region
         arena = self.base + offset
         x_ptr = arena + ab
         y_ptr = x_ptr + xb
@@ -377,11 +407,21 @@ class DnExecutor(Executor):
         dy = self.pool.narrow(0, offset + ab + xb, yb).view(torch.float32)
         ho = self.stage_out[slot][: yb // 4]
         with torch.cuda.stream(s):
-            dx.copy_(hx.view(-1), non_blocking=True)
+            t0 = torch.cuda.Event(enable_timing=True)
+            t0.record(s)
+            if direct:
+                dxv = dx.view(padded, c, size, size)
+                for j, im in enumerate(imgs):
+                    dxv[j].copy_(im, non_blocking=True)
+                if padded > len(imgs):
+                    dxv[len(imgs):].zero_()
+            else:
+                dx.copy_(hx.view(-1), non_blocking=True)
             self.net.forward_arena(arena, ab, x_ptr, padded, size, size, y_ptr, s)
             ho.copy_(dy, non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
+        self.intervals.append((t0, ev, padded))
         return (ev, slot, padded, size, oshape)
 
     def done(self, handle) -> bool:
@@ -393,6 +433,38 @@ class DnExecutor(Executor):
             out = self.stage_out[slot][: padded * oc * oh * ow].view(padded, oc, oh, ow)
             for j, r in enumerate(reqs):
                 r.output = out[j].numpy().copy()
+
+
+def device_overlap(intervals, ref_event) -> Dict[str, float]:
+    """Overlap of batches on the GPU from their event timestamps (all events
+    complete): each batch's interval runs from the event before its input copy
+    to the event after its output copy, in ms after ``ref_event`` (recorded
+    before any of them).  Returns the time the GPU held at least one batch
+    (busy_ms), the sum of the intervals, their ratio (mean batches in flight
+    while busy), the share of busy time with two or more batches in flight,
+    and the largest number in flight at once."""
+    ev = []
+    for t0, t1, _ in intervals:
+        a, b = ref_event.elapsed_time(t0), ref_event.elapsed_time(t1)
+        ev.append((a, 1))
+        ev.append((b, -1))
+    if not ev:
+        return {"busy_ms": 0.0, "sum_batch_ms": 0.0, "mean_in_flight": 0.0, "overlap_frac": 0.0, "max_in_flight": 0}
+    ev.sort(key=lambda e: (e[0], e[1]))  # an end before a start at the same instant
+    busy = multi = total = 0.0
+    depth = peak = 0
+    last = ev[0][0]
+    for t, d in ev:
+        if depth >= 1:
+            busy += t - last
+            total += (t - last) * depth
+        if depth >= 2:
+            multi += t - last
+        depth += d
+        peak = max(peak, depth)
+        last = t
+    return {"busy_ms": busy, "sum_batch_ms": total, "mean_in_flight": total / busy if busy else 0.0,
+            "overlap_frac": multi / busy if busy else 0.0, "max_in_flight": peak}
 
 
 def make_requests(trace, count: Optional[int] = None) -> List[Request]:

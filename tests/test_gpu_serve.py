@@ -62,3 +62,54 @@ def test_mixed_trace_completes_overlaps_and_matches_alone(env):
         err = G.rel_l2(r.output, ref)
         print("request %d S=%d vs oracle rel_l2 %.3e" % (r.rid, r.size, err))
         assert err < 2e-2
+
+
+def test_fixed_slots_replay_graphs_overlap_on_device_and_match_alone_bitwise(env):
+    """Fixed per-slot regions with captured graphs, on a batch-invariant net
+    whose frames arrive in pinned host buffers: once every (slot, batch, size)
+    graph is captured, a burst keeps several batches on the GPU at once (their
+    event intervals intersect), and each sampled request's output has the same
+    bits alone as in the mix."""
+    torch, dn, serve, net, params, _, image_of = env
+    pinned = {}
+
+    def frame(r):
+        key = (r.rid, r.size)
+        if key not in pinned:
+            pinned[key] = torch.from_numpy(synth.serving_image(r.rid, r.size).astype(np.float32)[0]).pin_memory()
+        return pinned[key]
+    mb = 16
+    n = dn.Net(net.layers, net.in_c, 608, 608, mb, dtype=dn.BF16, use_graph=True, batch_invariant=True)
+    n.load_params(params)
+    ex = serve.DnExecutor(n, torch, budget_bytes=0, n_slots=4, image_of=frame, max_batch=mb, max_size=608,
+                          fixed_slots=True, sizes=SIZES)
+    assert ex.pool.numel() == 4 * ex.region
+    for slot in range(4):
+        for size in SIZES:
+            for b in (1, 2, 4, 8, 16):
+                ex.launch(slot, [serve.Request(10 ** 6 + size, size, 0.0)], b, size, 0)[0].synchronize()
+    reqs = serve.make_requests(synth.serving_trace(300, 20000.0, synth.SEED_SERVING))
+    for r in reqs:  # the frames are in their pinned buffers before they arrive
+        frame(r)
+    ex.intervals.clear()
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record()
+    sch = serve.Scheduler(ex, ex.pool.numel(), SIZES, max_batch=mb)
+    st = sch.run(reqs)
+    torch.cuda.synchronize()
+    ov = serve.device_overlap(ex.intervals, ref)
+    print("fixed-slot serving 300 req: %s\ndevice: %s" % (st.as_dict(), ov))
+    errors = [r.error for r in reqs if r.error]
+    assert st.completed == 300 and st.failed == 0, errors[:3]
+    assert ov["max_in_flight"] >= 2 and ov["overlap_frac"] > 0.0, "batches never overlapped on the device"
+    picks = []
+    for s in SIZES:
+        picks += [r for r in reqs if r.size == s][:2]
+    for r in picks:
+        alone = serve.Request(r.rid, r.size, 0.0)
+        serve.Scheduler(ex, ex.pool.numel(), SIZES, max_batch=1).run([alone])
+        same = np.array_equal(r.output, alone.output)
+        print("request %d S=%d alone vs in the mix: bitwise %s" % (r.rid, r.size, same))
+        assert same
+    del ex
+    n.close()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from paper_1811_03882_amd.serve import (Executor, PoolAllocator, Request, Scheduler, make_requests,
+from paper_1811_03882_amd.serve import (Executor, PoolAllocator, Request, Scheduler, device_overlap, make_requests,
                                         next_pow2)
 
 
@@ -190,3 +190,30 @@ def test_budget_of_one_image_serves_a_burst_one_by_one():
     st = sch.run([Request(i, 608, 0.0) for i in range(9)])
     assert st.completed == 9 and sch.max_inflight == 1
     assert all(len(ids) == 1 for _, _, _, _, ids in ex.log)
+
+
+class _Ev:
+    """Stand-in for a completed timing event: elapsed_time(other) = other.t - self.t (ms)."""
+
+    def __init__(self, t):
+        self.t = t
+
+    def elapsed_time(self, other):
+        return other.t - self.t
+
+
+def test_device_overlap_from_event_intervals():
+    ref = _Ev(0.0)
+    # [1, 4], [2, 3], [3.5, 6], [8, 9]: busy 1..6 and 8..9 = 6 ms; two or more
+    # in flight over [2, 3] and [3.5, 4] = 1.5 ms; interval sum 3 + 1 + 2.5 + 1 = 7.5
+    iv = [(_Ev(1.0), _Ev(4.0), 1), (_Ev(2.0), _Ev(3.0), 1), (_Ev(3.5), _Ev(6.0), 1), (_Ev(8.0), _Ev(9.0), 1)]
+    d = device_overlap(iv, ref)
+    assert d["busy_ms"] == pytest.approx(6.0)
+    assert d["sum_batch_ms"] == pytest.approx(7.5)
+    assert d["mean_in_flight"] == pytest.approx(7.5 / 6.0)
+    assert d["overlap_frac"] == pytest.approx(1.5 / 6.0)
+    assert d["max_in_flight"] == 2
+    # back to back (one ends where the next starts): no overlap
+    d = device_overlap([(_Ev(0.0), _Ev(1.0), 1), (_Ev(1.0), _Ev(2.0), 1)], ref)
+    assert d["overlap_frac"] == 0.0 and d["max_in_flight"] == 1 and d["busy_ms"] == pytest.approx(2.0)
+    assert device_overlap([], ref)["busy_ms"] == 0.0
