@@ -169,14 +169,20 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
         t_setup = time.perf_counter()
         n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=True)
         n.load_params(params)
-        ex = serve.DnExecutor(n, torch, budget_bytes=0, n_slots=slots, image_of=image_of, max_batch=max_batch,
-                              max_size=max(sizes), keep_outputs=False, fixed_slots=True, sizes=sizes)
         batches = [1 << k for k in range(max_batch.bit_length()) if (1 << k) <= max_batch]
-        n.bind_arena(ex.pool, ex.region)  # slot 0's region while tuning
+        # tune first (in a scratch arena with room for split-K candidates): the
+        # executor sizes its slot regions from the tuned plans
+        scratch = torch.empty(2 * max(n.arena_bytes(max_batch, S, S) for S in sizes) + (512 << 20),
+                              dtype=torch.uint8, device="cuda")
+        n.bind_arena(scratch)
         for S in sizes:
             for b in batches:
                 n.autotune(b, S, S)
         torch.cuda.synchronize()
+        ex = serve.DnExecutor(n, torch, budget_bytes=0, n_slots=slots, image_of=image_of, max_batch=max_batch,
+                              max_size=max(sizes), keep_outputs=False, fixed_slots=True, sizes=sizes)
+        n.bind_arena(ex.pool, ex.region)
+        del scratch
         # warm-up: capture each slot's graph of every (batch, size), not counted
         for slot in range(slots):
             for S in sizes:

@@ -268,11 +268,18 @@ static bool invariant_tile_ok(int dt, int tile, int splits)
     return tile >= 0 && tile < tile_count() && (dt != BF16 || tile_cfg(tile).mf != 32);
 }
 
-// Which split convs finish in the GEMM launch itself (the last workgroup of
-// each output tile to arrive reduces that tile's partial sums).
+// Which split convs finish in the GEMM launch itself.  That finish runs on
+// the one workgroup per output tile that arrives last, which reads
+// splits x BM x BN partial sums.  Measured on the residual net's small-M
+// layers (batch 16) it beats the separate finish launch while that share is
+// at most 16K values (64x64 and 64x32 tiles up to 4 and 8 splits: by up to a
+// third of the layer's time) and loses to it beyond, by up to 20% (a few
+// large tiles leave the whole reduction to a few workgroups).
 static bool finish_in_kernel(int tile, int splits)
 {
-    return splits >= 2 && splits <= SPLITK_FUSED_MAX && !is_halo(tile) && tile >= 0 && tile < tile_count();
+    if (splits < 2 || splits > SPLITK_FUSED_MAX || is_halo(tile) || tile < 0 || tile >= tile_count()) return false;
+    const TileCfg t = tile_cfg(tile);
+    return (long)splits * t.bm * t.bn <= 16384;
 }
 
 // Fill ConvArgs for an op of plan p, reading from base (arena).

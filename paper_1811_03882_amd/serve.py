@@ -334,7 +334,8 @@ class DnExecutor(Executor):
     replayed.  Host images come from ``image_of`` (request -> float32
     [3, S, S], numpy or a pinned torch tensor): numpy images are copied into
     a per-slot pinned staging buffer and sent with one H2D copy per batch,
-    pinned tensors with one H2D copy each.
+    pinned tensors with one H2D copy each.  Region sizes come from the net's
+    plans when the executor is created: tune the net first.
     """
 
     def __init__(self, net, torch, budget_bytes: int, n_slots: int, image_of: Callable[[Request], np.ndarray],
