@@ -143,7 +143,7 @@ def cpu_baseline(budget_s: float = 12.0):
 
 
 def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
-            sweep=(("bf16_continuous_batching", (4000.0, 8000.0, 16000.0, 32000.0)),
+            sweep=(("bf16_continuous_batching", (4000.0, 8000.0, 16000.0, 32000.0, 48000.0)),
                    ("f32_plain_batch1", (1000.0, 2000.0, 4000.0, 8000.0)))):
     """Open-loop serving of the mixed-resolution trace: BF16 continuous batching
     (8 slots, batches padded to powers of two up to 64) vs the FP32 plain path

@@ -31,6 +31,7 @@ fake executor implement.
 from __future__ import annotations
 
 import bisect
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -286,9 +287,19 @@ class Scheduler:
         return launched
 
     # -- open-loop driver
-    def run(self, reqs: Sequence[Request], idle_sleep: float = 0.0) -> ServeStats:
+    def run(self, reqs: Sequence[Request], idle_sleep: float = 0.0, hold_gc: bool = True) -> ServeStats:
         """Feed requests at their arrival times (scheduler clock relative to the
-        start) and run until every request completed or was rejected."""
+        start) and run until every request completed or was rejected.  With
+        hold_gc, Python's cyclic garbage collector is paused for the run (and
+        run once after it): a full collection over the run's objects would
+        stall the loop for tens of milliseconds."""
+        if hold_gc and gc.isenabled():
+            gc.disable()
+            try:
+                return self.run(reqs, idle_sleep, hold_gc=False)
+            finally:
+                gc.enable()
+                gc.collect()
         order = sorted(reqs, key=lambda r: r.arrival)
         t0 = self.clock()
         for r in order:
