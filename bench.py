@@ -65,9 +65,10 @@ def conv_flops(net, batch, h, w):
     return out
 
 
-def build_net(dn, torch, net, dtype, batch, h, w, params, use_graph=True, tune=True, mode=0, calib=None):
+def build_net(dn, torch, net, dtype, batch, h, w, params, use_graph=True, tune=True, mode=0, calib=None,
+              input_u8=False):
     n = dn.Net(net.layers, net.in_c, h, w, batch, dtype=dtype, mode=mode, leaky_slope=net.leaky_slope,
-               bn_eps=net.bn_eps, use_graph=use_graph)
+               bn_eps=net.bn_eps, use_graph=use_graph, input_u8=input_u8)
     n.load_params(params)
     if dtype == dn.FP8:
         n.calibrate(calib, calib.shape[0], h, w)
@@ -144,6 +145,7 @@ def cpu_baseline(budget_s: float = 12.0):
 
 def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
             sweep=(("bf16_continuous_batching", (4000.0, 8000.0, 16000.0, 32000.0, 48000.0)),
+                   ("bf16_continuous_batching_u8frames", (8000.0, 16000.0, 32000.0, 48000.0, 64000.0, 96000.0)),
                    ("f32_plain_batch1", (1000.0, 2000.0, 4000.0, 8000.0)))):
     """Open-loop serving of the mixed-resolution trace: BF16 continuous batching
     (8 slots, batches padded to powers of two up to 64) vs the FP32 plain path
@@ -157,17 +159,24 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
     net = synth.plain9()
     params = synth.make_params(net, synth.SEED_PLAIN)
     sizes = synth.serving_trace(1, rate, synth.SEED_SERVING).sizes
-    # camera frames arrive in pinned host buffers (8 distinct frames per size)
-    pool = {s: [torch.from_numpy(synth.serving_image(1000000 + 8 * j + k, s).astype(np.float32)[0]).pin_memory()
-                for k in range(8)] for j, s in enumerate(sizes)}
-    image_of = lambda r: pool[r.size][r.rid % 8]
+    # camera frames arrive in pinned host buffers (8 distinct frames per size),
+    # as FP32 or as the 8-bit pixels they are quantised from
+    frames = {s: [synth.serving_image(1000000 + 8 * j + k, s).astype(np.float32)[0] for k in range(8)]
+              for j, s in enumerate(sizes)}
+    pool = {s: [torch.from_numpy(f).pin_memory() for f in fs] for s, fs in frames.items()}
+    pool8 = {s: [torch.from_numpy(np.round(f * 255.0).astype(np.uint8)).pin_memory() for f in fs]
+             for s, fs in frames.items()}
     rates = dict(sweep)
     out = {}
-    for name, dtype, slots, max_batch, bucketed in (("bf16_continuous_batching", dn.BF16, 8, 64, True),
-                                                    ("f32_plain_batch1", dn.F32, 1, 1, False)):
+    for name, dtype, slots, max_batch, bucketed, u8 in (("bf16_continuous_batching", dn.BF16, 8, 64, True, False),
+                                                        ("bf16_continuous_batching_u8frames", dn.BF16, 8, 64, True, True),
+                                                        ("f32_plain_batch1", dn.F32, 1, 1, False, False)):
         log("[bench] serving %s" % name)
         t_setup = time.perf_counter()
-        n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=True)
+        src = pool8 if u8 else pool
+        image_of = lambda r, src=src: src[r.size][r.rid % 8]
+        n = dn.Net(net.layers, net.in_c, max(sizes), max(sizes), max_batch, dtype=dtype, use_graph=True,
+                   input_u8=u8)
         n.load_params(params)
         batches = [1 << k for k in range(max_batch.bit_length()) if (1 << k) <= max_batch]
         # tune first (in a scratch arena with room for split-K candidates): the
@@ -205,7 +214,7 @@ def serving(torch, dn, n_requests: int = 10000, rate: float = 2000.0, log=print,
             return d
         d = run(rate, n_requests)
         d.update({"dtype": {0: "f32", 1: "bf16"}[dtype], "slots": slots, "graph": True, "tuned": True,
-                  "budget_gb": ex.pool.numel() / 2 ** 30, "setup_s": t_setup})
+                  "frames": "uint8" if u8 else "fp32", "budget_gb": ex.pool.numel() / 2 ** 30, "setup_s": t_setup})
         log("[bench]   %s" % d)
         points = []
         for r in rates.get(name, ()):
@@ -742,6 +751,27 @@ def main():
         secondary.append({"workload": "9-layer b64 bf16 graph incl. PCIe (pinned H2D of the FP32 batch + D2H of the output)",
                           "images_per_s": B * 10 / wp, "ms_per_step": wp * 1e3 / 10})
         log("[bench] bf16 b64 incl. PCIe: %.3f ms/step" % (wp * 1e3 / 10))
+        # the same with 8-bit frames (a camera's pixels, q / 255 on the device): a quarter of the H2D bytes
+        n8, a8 = build_net(dn, torch, net, dn.BF16, B, H, W, params, input_u8=True)
+        q = np.random.default_rng([synth.SEED_PLAIN, 9]).integers(0, 256, size=(B, net.in_c, H, W), dtype=np.uint8)
+        xh8 = torch.from_numpy(q).pin_memory()
+        x8 = torch.empty(xh8.shape, dtype=torch.uint8, device="cuda")
+
+        def fwd_pcie8():
+            x8.copy_(xh8, non_blocking=True)
+            n8.forward(x8, B, H, W, y, stream)
+            yh.copy_(y, non_blocking=True)
+
+        with torch.cuda.stream(stream):
+            wp8, _ = time_steps(torch, fwd_pcie8, 10, 2, stream)
+            w8, _ = time_steps(torch, lambda: n8.forward(x8, B, H, W, y, stream), 10, 2, stream)
+        secondary.append({"workload": "9-layer b64 bf16 graph incl. PCIe, 8-bit frames (pinned H2D of the uint8 batch, "
+                                      "converted on the device, + D2H of the output)",
+                          "images_per_s": B * 10 / wp8, "ms_per_step": wp8 * 1e3 / 10,
+                          "device_resident_images_per_s": B * 10 / w8})
+        log("[bench] bf16 b64 incl. PCIe, 8-bit frames: %.3f ms/step (resident %.3f ms)" % (wp8 * 1e3 / 10, w8 * 1e3 / 10))
+        n8.close()
+        del a8, x8, xh8
         calib = torch.from_numpy(synth.make_input(net, 4, synth.SEED_CALIB).astype(np.float32)).cuda()
         for name, dt in (("fp8", dn.FP8), ("f32", dn.F32)):
             log("[bench] %s b64" % name)

@@ -83,7 +83,9 @@ typedef struct dn_net_opts {
     float leaky_slope;   /* 0.1 for the Darknet leaky rectifier */
     double bn_eps;       /* batch-norm epsilon (1e-5) */
     int use_graph;       /* 1: resident forwards are captured once per
-                            (batch, h, w, x, y, arena) into a hipGraph and replayed */
+                            (batch, h, w, x, y, arena) into a hipGraph and replayed;
+                            at most 4096 are kept per net, later new buffers
+                            run without capture */
     int device;          /* HIP device ordinal */
     int batch_invariant; /* 1: every output element is reduced in an order that
                             does not depend on the batch size, so an image gives
@@ -92,6 +94,11 @@ typedef struct dn_net_opts {
                             K alone (dn_layer_plan reports it) and only tiles of
                             16x16 MFMA blocks run; tiles may still differ with
                             the batch.  0: tiles and splits tuned per batch. */
+    int input_u8;        /* 1 (resident mode only): the x of dn_forward and
+                            dn_forward_arena is NCHW 8-bit pixels, value q / 255
+                            (a camera frame), converted on the device; the
+                            image crosses PCIe at a quarter of the FP32 bytes.
+                            0: NCHW FP32. */
 } dn_net_opts;
 
 typedef struct dn_net dn_net;
@@ -132,8 +139,8 @@ dn_status dn_load_weights(dn_net *net, int layer, const double *w, const double 
  * activation tensor, scale = amax / 448.  Synchronous. */
 dn_status dn_calibrate(dn_net *net, const float *x, int batch, int h, int w, void *stream);
 
-/* Forward.  Resident mode: x and y are device pointers (NCHW FP32, y of
- * dn_net_output_shape); one ingest, the conv/pool/shortcut kernels and one
+/* Forward.  Resident mode: x and y are device pointers (x NCHW FP32, or
+ * NCHW uint8 for an input_u8 net; y NCHW FP32 of dn_net_output_shape); one ingest, the conv/pool/shortcut kernels and one
  * egress are enqueued on `stream` with no host synchronisation and no
  * allocation (or one hipGraphLaunch when use_graph is set).
  * Per-layer mode: x and y are host pointers; every layer's input and weights

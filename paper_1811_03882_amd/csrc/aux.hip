@@ -108,8 +108,10 @@ hipError_t launch_fold_pack(int dt, int mode, const double *w, const double *bia
 // NCHW FP32 -> NHWC storage type.  One thread per (pixel, 16-byte segment):
 // consecutive threads read consecutive pixels of one channel plane.
 
+// x8 set: the source is 8-bit pixels, value q / 255 (x unused).
 template <int DT>
-__global__ void __launch_bounds__(256) ingest(const float *x, int n, int c, int hw, int cp, float inv_scale, void *y)
+__global__ void __launch_bounds__(256) ingest(const float *x, const unsigned char *x8, int n, int c, int hw, int cp,
+                                              float inv_scale, void *y)
 {
     constexpr int E = Seg<DT>::N;
     const int nseg = cp / E;
@@ -124,21 +126,22 @@ __global__ void __launch_bounds__(256) ingest(const float *x, int n, int c, int 
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int ch = sg * E + e;
-        f[e] = ch < c ? x[((size_t)img * c + ch) * hw + p] * inv_scale : 0.0f;
+        const size_t i = ((size_t)img * c + ch) * hw + p;
+        f[e] = ch < c ? (x8 ? __fdiv_rn((float)x8[i], 255.0f) : x[i]) * inv_scale : 0.0f;
     }
     ((uint4 *)y)[((size_t)img * hw + p) * nseg + sg] = Seg<DT>::enc(f);
 }
 
 hipError_t launch_ingest(int dt, const float *x, int n, int c, int h, int w, int cp, float inv_scale,
-                         void *y, hipStream_t s)
+                         void *y, hipStream_t s, const unsigned char *x8)
 {
     const size_t total = (size_t)n * h * w * (cp / seg_el(dt));
     if (total == 0) return hipSuccess;
     dim3 g((unsigned)((total + 255) / 256)), b(256);
     switch (dt) {
-    case F32: hipLaunchKernelGGL(ingest<F32>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
-    case BF16: hipLaunchKernelGGL(ingest<BF16>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
-    case FP8: hipLaunchKernelGGL(ingest<FP8>, g, b, 0, s, x, n, c, h * w, cp, inv_scale, y); break;
+    case F32: hipLaunchKernelGGL(ingest<F32>, g, b, 0, s, x, x8, n, c, h * w, cp, inv_scale, y); break;
+    case BF16: hipLaunchKernelGGL(ingest<BF16>, g, b, 0, s, x, x8, n, c, h * w, cp, inv_scale, y); break;
+    case FP8: hipLaunchKernelGGL(ingest<FP8>, g, b, 0, s, x, x8, n, c, h * w, cp, inv_scale, y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -889,7 +889,8 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
         constexpr int PB = 32 / CP;
         const int npix = LH * LW;
         const size_t plane = (size_t)a.H * a.W;
-        const float *xn = a.x + (size_t)n * a.C * plane;
+        const float *xn = a.x ? a.x + (size_t)n * a.C * plane : nullptr;
+        const unsigned char *xn8 = a.x8 ? a.x8 + (size_t)n * a.C * plane : nullptr;
         int lr = tid / LW, lc = tid % LW;
         const int dlr = 256 / LW, dlc = 256 % LW;
         for (int base = 0; base < npix; base += 256 * PB) {
@@ -900,7 +901,8 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 const bool ok = base + j * 256 + tid < npix && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
                 const size_t o = ok ? (size_t)hi * a.W + wi : 0;
 #pragma unroll
-                for (int c = 0; c < CP; ++c) v[j][c] = (ok && c < a.C) ? xn[o + c * plane] : 0.0f;
+                for (int c = 0; c < CP; ++c)
+                    v[j][c] = (ok && c < a.C) ? (xn8 ? __fdiv_rn((float)xn8[o + c * plane], 255.0f) : xn[o + c * plane]) : 0.0f;
                 lc += dlc; lr += dlr;
                 if (lc >= LW) { lc -= LW; ++lr; }
             }
@@ -1760,6 +1762,13 @@ static const TileCfg kTiles[] = {
     {176, 128, 1, 4},      // 40: 2 stages, 4 waves of 176x32
     {192, 128, 2, 2, 32},  // 41: 2 stages, 4 waves of 96x64
     {192, 128, 2, 4, 32},  // 42: 2 stages, 8 waves of 96x32
+    // small LDS-DMA tiles for small-M layers: deep pipelines in 48-64 KB, so
+    // two or three workgroups share a CU and keep more K-tiles in flight
+    {64, 64, 2, 2},        // 43: 4 stages, 4 waves of 32x32
+    {64, 64, 2, 2},        // 44: 3 stages
+    {128, 64, 2, 2},       // 45: 4 stages, 4 waves of 64x32
+    {64, 128, 2, 2},       // 46: 4 stages, 4 waves of 32x64
+    {64, 32, 2, 2},        // 47: 4 stages, 4 waves of 32x16
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -1854,6 +1863,11 @@ static hipError_t dispatch(int tile, const ConvArgs &a, hipStream_t s)
     case 40: return go_dl<DT, 176, 128, 1, 4, 2>(a, s);
     case 41: return go_dl<DT, 192, 128, 2, 2, 2, 8, 32>(a, s);
     case 42: return go_dl<DT, 192, 128, 2, 4, 2, 8, 32>(a, s);
+    case 43: return go_dl<DT, 64, 64, 2, 2, 4>(a, s);
+    case 44: return go_dl<DT, 64, 64, 2, 2, 3>(a, s);
+    case 45: return go_dl<DT, 128, 64, 2, 2, 4>(a, s);
+    case 46: return go_dl<DT, 64, 128, 2, 2, 4>(a, s);
+    case 47: return go_dl<DT, 64, 32, 2, 2, 4>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -66,6 +66,7 @@ struct ConvArgs {
 // Weights packed in the order k = r*16 + s*CP + c, CP = first_cp(C), k_pad = first_kpad().
 struct FirstArgs {
     const float *x;        // NCHW FP32 image batch
+    const unsigned char *x8;  // or, when set, NCHW 8-bit pixels with value q / 255
     const void *w;
     const float *bias, *wscale;
     void *y;               // NHWC output (pooled when pool = 1)
@@ -124,8 +125,9 @@ hipError_t launch_fold_pack(int dt, int mode, const double *w, const double *bia
                             double eps, int has_bn, int cout, int cin, int R, int S, int cin_p,
                             int k_pad, int cout_p, void *wout, float *bout, float *sout,
                             hipStream_t s);
+// x8 set: the source is NCHW 8-bit pixels with value q / 255 (x unused).
 hipError_t launch_ingest(int dt, const float *x, int n, int c, int h, int w, int cp,
-                         float inv_scale, void *y, hipStream_t s);
+                         float inv_scale, void *y, hipStream_t s, const unsigned char *x8 = nullptr);
 hipError_t launch_egress(int dt, const void *x, int n, int c, int h, int w, int cp, float scale,
                          float *y, hipStream_t s);
 hipError_t launch_maxpool(int dt, const void *x, void *y, int n, int h, int w, int cp, int size,

@@ -548,13 +548,15 @@ static dn_status make_plan(const dn_net *net, int dtype, int mode, int batch, in
 
 // ---------------------------------------------------------------- enqueue
 
+// x8 set: the image is 8-bit pixels (value q / 255) instead of FP32 x.
 static dn_status enqueue_first(const dn_net *net, const Plan &p, const Op &op, const float *x, char *base,
-                               hipStream_t s, bool use32)
+                               hipStream_t s, bool use32, const unsigned char *x8 = nullptr)
 {
     const dn_layer_desc &d = net->L[op.conv];
     const ConvWeights &cw = net->cw[op.conv];
     FirstArgs a{};
-    a.x = x;
+    a.x = x8 ? nullptr : x;
+    a.x8 = x8;
     a.w = use32 ? cw.w32 : cw.w;
     a.bias = use32 ? cw.bias32 : cw.bias;
     a.wscale = use32 ? cw.wscale32 : cw.wscale;
@@ -580,11 +582,12 @@ static dn_status enqueue_first(const dn_net *net, const Plan &p, const Op &op, c
 }
 
 static dn_status enqueue_op(const dn_net *net, const Plan &p, const Op &op, char *base, hipStream_t s, bool use32,
-                            int tile_override = -1, int splits_override = 0, const float *xin = nullptr)
+                            int tile_override = -1, int splits_override = 0, const float *xin = nullptr,
+                            const unsigned char *xin8 = nullptr)
 {
     if (op.kind == OP_CONV && op.first) {
-        if (!xin) return fail(DN_EINVAL, "first-layer kernel needs the input image");
-        return enqueue_first(net, p, op, xin, base, s, use32);
+        if (!xin && !xin8) return fail(DN_EINVAL, "first-layer kernel needs the input image");
+        return enqueue_first(net, p, op, xin, base, s, use32, xin8);
     }
     if (op.kind == OP_CONV) {
         Op o2 = op;
@@ -625,9 +628,12 @@ static dn_status enqueue_resident(const dn_net *net, const Plan &p, char *base, 
     if (p.any_fused) STCHK(zero_counters(p, base, s));
     const Value &v0 = p.vals[0];
     const float in_inv = p.dtype == FP8 ? 1.0f / net->scale[0] : 1.0f;
+    // 8-bit input nets: x holds the NCHW frames as bytes, converted on the device
+    const unsigned char *x8 = net->o.input_u8 ? (const unsigned char *)x : nullptr;
+    const float *xf = x8 ? nullptr : x;
     if (!p.ops[0].first)
-        HIPCHK(launch_ingest(p.dtype, x, p.batch, v0.c, v0.h, v0.w, v0.cp, in_inv, base + v0.off, s));
-    for (const Op &op : p.ops) STCHK(enqueue_op(net, p, op, base, s, false, -1, 0, x));
+        HIPCHK(launch_ingest(p.dtype, xf, p.batch, v0.c, v0.h, v0.w, v0.cp, in_inv, base + v0.off, s, x8));
+    for (const Op &op : p.ops) STCHK(enqueue_op(net, p, op, base, s, false, -1, 0, xf, x8));
     const Value &vo = p.vals[p.out_val];
     const float osc = p.dtype == FP8 ? net->scale[p.out_val] : 1.0f;
     HIPCHK(launch_egress(p.dtype, base + vo.off, p.batch, vo.c, vo.h, vo.w, vo.cp, osc, y, s));
@@ -673,6 +679,7 @@ extern "C" dn_status dn_net_create(const dn_layer_desc *layers, int n, const dn_
     if (!layers || n <= 0 || !o) return fail(DN_EINVAL, "need a non-empty layer list and options");
     STCHK(check_dtype(o->dtype));
     if (o->mode != DN_MODE_RESIDENT && o->mode != DN_MODE_PER_LAYER) return fail(DN_EINVAL, "unknown mode %d", o->mode);
+    if (o->input_u8 && o->mode != DN_MODE_RESIDENT) return fail(DN_EUNSUPPORTED, "8-bit input needs a resident-mode net");
     if (o->in_c <= 0 || o->in_c > 16) return fail(DN_EINVAL, "in_c %d outside 1..16", o->in_c);
     if (o->max_h <= 0 || o->max_w <= 0 || o->max_batch <= 0) return fail(DN_EINVAL, "max_h/max_w/max_batch must be positive");
     if (!(o->bn_eps > 0.0)) return fail(DN_EINVAL, "bn_eps must be > 0");
@@ -927,6 +934,11 @@ static dn_status resident_plan(dn_net *net, int batch, int h, int w, std::shared
     return DN_OK;
 }
 
+// Captured forwards kept per net (two executable instances each).  Callers
+// whose buffers repeat (fixed serving slots) stay far below it; buffers that
+// never repeat would otherwise grow the cache without bound.
+constexpr size_t MAX_GRAPHS = 4096;
+
 static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, const void *x, int batch, int h,
                                   int w, void *y, hipStream_t s)
 {
@@ -958,7 +970,13 @@ static dn_status forward_resident(dn_net *net, void *arena, size_t arena_bytes, 
     STCHK(resident_plan(net, batch, h, w, &pp));
     const Plan &p = *pp;
     if (arena_bytes < p.total) return fail(DN_ENOMEM, "arena has %zu bytes, plan needs %zu", arena_bytes, p.total);
-    if (!net->o.use_graph) return enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, s);
+    bool full;
+    {
+        std::lock_guard<std::mutex> g(net->mu);
+        full = net->graphs.size() >= MAX_GRAPHS;
+    }
+    // without graphs, or with the cache full (buffers that never repeat), launch eagerly
+    if (!net->o.use_graph || full) return enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, s);
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
     dn_status rc = enqueue_resident(net, p, (char *)arena, (const float *)x, (float *)y, net->cap_stream);
@@ -1181,6 +1199,7 @@ static dn_status placed_check(const dn_net *net, const unsigned char *gene, int 
 {
     if (net->o.dtype != DN_F32) return fail(DN_EUNSUPPORTED, "layer placement needs an FP32 net");
     if (net->o.mode != DN_MODE_RESIDENT) return fail(DN_EUNSUPPORTED, "layer placement needs a resident-mode net");
+    if (net->o.input_u8) return fail(DN_EUNSUPPORTED, "layer placement takes an FP32 image");
     if (!gene) return DN_OK;
     if (gene_len != (int)net->L.size())
         return fail(DN_EINVAL, "gene has %d values, the net has %zu layers", gene_len, net->L.size());

@@ -42,7 +42,8 @@ class NetOpts(ctypes.Structure):
     _fields_ = [("in_c", ctypes.c_int), ("max_h", ctypes.c_int), ("max_w", ctypes.c_int),
                 ("max_batch", ctypes.c_int), ("dtype", ctypes.c_int), ("mode", ctypes.c_int),
                 ("leaky_slope", ctypes.c_float), ("bn_eps", ctypes.c_double),
-                ("use_graph", ctypes.c_int), ("device", ctypes.c_int), ("batch_invariant", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("device", ctypes.c_int), ("batch_invariant", ctypes.c_int),
+                ("input_u8", ctypes.c_int)]
 
 
 class ConvDesc(ctypes.Structure):
@@ -269,12 +270,14 @@ class Net:
 
     def __init__(self, layers: Sequence, in_c: int, max_h: int, max_w: int, max_batch: int,
                  dtype: int = F32, mode: int = RESIDENT, leaky_slope: float = 0.1,
-                 bn_eps: float = 1e-5, use_graph: bool = False, device: int = 0, batch_invariant: bool = False):
+                 bn_eps: float = 1e-5, use_graph: bool = False, device: int = 0, batch_invariant: bool = False,
+                 input_u8: bool = False):
         self.layers = list(layers)
         self.dtype, self.mode = dtype, mode
         self.in_c = in_c
         opts = NetOpts(in_c, max_h, max_w, max_batch, dtype, mode, leaky_slope, bn_eps,
-                       int(bool(use_graph)), device, int(bool(batch_invariant)))
+                       int(bool(use_graph)), device, int(bool(batch_invariant)), int(bool(input_u8)))
+        self.input_u8 = bool(input_u8)
         h = _vp()
         descs = layer_descs(self.layers)
         check(LIB.dn_net_create(descs, len(self.layers), ctypes.byref(opts), ctypes.byref(h)))

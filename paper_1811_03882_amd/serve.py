@@ -359,6 +359,10 @@ class DnExecutor(Executor):
         self.keep = keep_outputs
         self.fixed = fixed_slots
         self._layout = {}
+        # an input_u8 net takes its frames as 8-bit pixels
+        self.in_u8 = bool(getattr(net, "input_u8", False))
+        self.in_dtype = torch.uint8 if self.in_u8 else torch.float32
+        self.in_bytes = 1 if self.in_u8 else 4
         if fixed_slots:
             self.region = max(self._bytes(max_batch, s) for s in (sizes or (max_size,)))
             budget_bytes = self.region * n_slots
@@ -367,7 +371,7 @@ class DnExecutor(Executor):
         self.intervals = []  # (start event, end event, padded batch) of every launched batch
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         c = net.in_c
-        self.stage_in = [torch.empty((max_batch, c, max_size, max_size), dtype=torch.float32).pin_memory()
+        self.stage_in = [torch.empty((max_batch, c, max_size, max_size), dtype=self.in_dtype).pin_memory()
                          for _ in range(n_slots)]
         oc, oh, ow = net.output_shape(max_size, max_size)
         self.stage_out = [torch.empty((max_batch * oc * oh * ow,), dtype=torch.float32).pin_memory()
@@ -378,7 +382,7 @@ class DnExecutor(Executor):
         if key not in self._layout:
             ab = self.net.arena_bytes(batch, size, size)
             ab = (ab + 255) // 256 * 256
-            xb = batch * self.net.in_c * size * size * 4
+            xb = batch * self.net.in_c * size * size * self.in_bytes
             xb = (xb + 255) // 256 * 256
             oc, oh, ow = self.net.output_shape(size, size)
             yb = batch * oc * oh * ow * 4
@@ -415,7 +419,7 @@ class DnExecutor(Executor):
         x_ptr = arena + ab
         y_ptr = x_ptr + xb
         n = padded * c * size * size
-        dx = self.pool.narrow(0, offset + ab, n * 4).view(torch.float32)
+        dx = self.pool.narrow(0, offset + ab, n * self.in_bytes).view(self.in_dtype)
         dy = self.pool.narrow(0, offset + ab + xb, yb).view(torch.float32)
         ho = self.stage_out[slot][: yb // 4]
         with torch.cuda.stream(s):

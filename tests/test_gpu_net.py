@@ -274,3 +274,40 @@ def test_tune_cache_is_keyed_by_device(dn, tmp_path, monkeypatch):
     text = path.read_text()
     assert all(f in text for f in foreign)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("which,dtype", [("plain9", 1), ("plain9", 0), ("ingest", 1), ("ingest", 0)])
+def test_u8_frames_give_the_bits_of_their_fp32_values(dn, which, dtype):
+    """An input_u8 net converts 8-bit frames on the device (q / 255, rounded to
+    nearest): its output equals, bit for bit, the FP32-input net's on the
+    FP32 values q / 255; through the fused first-layer kernel (9-layer net)
+    and through the separate ingest (first conv too wide for that kernel)."""
+    torch = G.torch_cuda()
+    if which == "plain9":
+        net, b, h, w = synth.plain9(), 3, 96, 128
+    else:
+        net, b, h, w = synth.Net("wide_first", 3, 40, 56, [synth.conv(96, 3), synth.maxpool(), synth.conv(40, 1)]), 2, 40, 56
+    params = synth.make_params(net, 17)
+    q = np.random.default_rng([17, 8]).integers(0, 256, size=(b, net.in_c, h, w), dtype=np.uint8)
+    xf = q.astype(np.float32) / np.float32(255.0)
+    outs = []
+    for u8 in (False, True):
+        n = dn.Net(net.layers, net.in_c, h, w, b, dtype=dtype, use_graph=True, input_u8=u8)
+        n.load_params(params)
+        arena = G.empty_bytes(n.arena_bytes(b, h, w))
+        n.bind_arena(arena)
+        y = torch.empty((b,) + n.output_shape(h, w), dtype=torch.float32, device="cuda")
+        for _ in range(2):  # capture, then replay
+            y.fill_(float("nan"))
+            n.forward(G.dev(q) if u8 else G.dev(xf), b, h, w, y)
+            torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+        n.close()
+    assert np.array_equal(outs[0], outs[1])
+    ref = onet.forward(net, params, q.astype(np.float64) / 255.0)[-1]
+    err = G.rel_l2(outs[1], ref)
+    print("%s %s u8 frames vs oracle rel_l2 %.3e" % (which, G.NAME[dtype], err))
+    assert err < G.GATE[dtype]
+    with pytest.raises(dn.DnError) as e:
+        dn.Net(net.layers, net.in_c, h, w, b, dtype=dtype, mode=dn.PER_LAYER, input_u8=True)
+    assert e.value.status == dn.DN_EUNSUPPORTED
