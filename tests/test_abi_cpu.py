@@ -195,3 +195,43 @@ def test_committed_traffic_profile_is_well_formed():
         assert e["hbm_bytes_per_launch"] > 63.2e6
         assert abs(e["fetch"]["factor"] - 0.5) < 0.01 and abs(e["write"]["factor"] - 1.0) < 0.01
         assert e["kernel"].startswith("void dnk::conv_igemm_dl<1,")
+
+
+def test_binding_structs_match_the_header(dn, tmp_path):
+    """Every struct the binding passes across the boundary has the header's
+    fields, in the header's order, at the header's offsets and size: a C
+    program built against include/dn.h prints them (offsetof / sizeof) and
+    they are compared with the ctypes mirrors."""
+    import subprocess
+    pairs = {"dn_layer_desc": dn.LayerDesc, "dn_net_opts": dn.NetOpts, "dn_conv_desc": dn.ConvDesc,
+             "dn_pool_desc": dn.PoolDesc, "dn_ga_params": dn.GaParams, "dn_ga_result": dn.GaResult}
+    src = open(HEADER).read()
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dn.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), src, flags=re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            names += [re.sub(r"[\s*]", "", n).split("[")[0] for n in re.sub(r"^[A-Za-z_ ]+?\s+(?=\**\w+\s*(,|$))", "", decl).split(",")]
+        assert [f[0] for f in cls._fields_] == names, (cname, names)
+        lines.append('printf("%s .sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for n in names:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, n, cname, n))
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, cls in pairs.items():
+        assert got[(cname, ".sizeof")] == ctypes.sizeof(cls), cname
+        for n, _ in cls._fields_:
+            assert got[(cname, n)] == getattr(cls, n).offset, (cname, n)
