@@ -235,3 +235,31 @@ def test_binding_structs_match_the_header(dn, tmp_path):
         assert got[(cname, ".sizeof")] == ctypes.sizeof(cls), cname
         for n, _ in cls._fields_:
             assert got[(cname, n)] == getattr(cls, n).offset, (cname, n)
+
+
+def test_halo_kernel_eligibility(dn):
+    """Host-side eligibility of the two halo kernels over the GPU tests' shape
+    list: every shape either qualifies or is rejected with DN_EUNSUPPORTED
+    (never another error); the 9-layer net's c2 / c3 classes qualify for the
+    persistent kernel in BF16 and FP8, and its FP32 instances (whose K steps
+    exceed the weights it keeps in registers) are rejected."""
+    from tests.test_gpu_layers import HALO, HALO_BIG, HALO_TILE, HALO2_TILE
+    ok = set()
+    for shape in HALO + HALO_BIG:
+        b, h, w, cin, cout, k, st, pad, pool, resid = shape
+        for dtype in (dn.F32, dn.BF16, dn.FP8):
+            for tile in (HALO_TILE, HALO2_TILE):
+                d = dn.conv_desc(b, h, w, cin, cout, k, st, pad, 1, 0.1, 2 if pool else 0, resid, dtype,
+                                 tile=tile, splits=1)
+                try:
+                    dn.conv_sizes(d)
+                    ok.add((shape, dtype, tile))
+                except dn.DnError as e:
+                    assert e.status == dn.DN_EUNSUPPORTED, (shape, dtype, tile, e)
+    for shape in HALO_BIG:
+        for dtype in (dn.BF16, dn.FP8):
+            assert (shape, dtype, HALO2_TILE) in ok
+        assert (shape, dn.F32, HALO2_TILE) not in ok
+    # three 16-channel blocks (48 output channels) run on the earlier halo kernel only
+    assert ((1, 17, 19, 16, 48, 3, 2, 1, 0, 0), dn.BF16, HALO_TILE) in ok
+    assert ((1, 17, 19, 16, 48, 3, 2, 1, 0, 0), dn.BF16, HALO2_TILE) not in ok
