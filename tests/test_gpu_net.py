@@ -276,7 +276,7 @@ def test_tune_cache_is_keyed_by_device(dn, tmp_path, monkeypatch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("which,dtype", [("plain9", 1), ("plain9", 0), ("ingest", 1), ("ingest", 0)])
+@pytest.mark.parametrize("which,dtype", [("plain9", 1), ("plain9", 0), ("plain9", 2), ("ingest", 1), ("ingest", 0)])
 def test_u8_frames_give_the_bits_of_their_fp32_values(dn, which, dtype):
     """An input_u8 net converts 8-bit frames on the device (q / 255, rounded to
     nearest): its output equals, bit for bit, the FP32-input net's on the
@@ -294,6 +294,8 @@ def test_u8_frames_give_the_bits_of_their_fp32_values(dn, which, dtype):
     for u8 in (False, True):
         n = dn.Net(net.layers, net.in_c, h, w, b, dtype=dtype, use_graph=True, input_u8=u8)
         n.load_params(params)
+        if dtype == dn.FP8:  # the activation scales come from an FP32 calibration input either way
+            n.calibrate(G.dev(xf), b, h, w)
         arena = G.empty_bytes(n.arena_bytes(b, h, w))
         n.bind_arena(arena)
         y = torch.empty((b,) + n.output_shape(h, w), dtype=torch.float32, device="cuda")
@@ -307,7 +309,8 @@ def test_u8_frames_give_the_bits_of_their_fp32_values(dn, which, dtype):
     ref = onet.forward(net, params, q.astype(np.float64) / 255.0)[-1]
     err = G.rel_l2(outs[1], ref)
     print("%s %s u8 frames vs oracle rel_l2 %.3e" % (which, G.NAME[dtype], err))
-    assert err < G.GATE[dtype]
+    if dtype != dn.FP8:  # FP8 is gated per layer (end to end it is reported only, as for FP32 frames)
+        assert err < G.GATE[dtype]
     with pytest.raises(dn.DnError) as e:
         dn.Net(net.layers, net.in_c, h, w, b, dtype=dtype, mode=dn.PER_LAYER, input_u8=True)
     assert e.value.status == dn.DN_EUNSUPPORTED
