@@ -602,8 +602,9 @@ template <int SPR> __device__ __forceinline__ int seg_swz(int row)
 }
 
 // MF = 16: 16x16 MFMA blocks (every dtype); MF = 32: 32x32x16 BF16 blocks,
-// which gfx950 issues at twice the rate of 16x16x32 BF16 (same passes for
-// twice the products).  A 32x32 fragment: lane l holds row l%32 and K
+// which take twice the passes of a 16x16x32 block for twice the products
+// (the same rate) but read each 1 KB operand fragment for twice the work, so
+// a tile needs half the LDS reads per product.  A 32x32 fragment: lane l holds row l%32 and K
 // elements [8*(l/32), 8*(l/32) + 8) of the 16-element step, i.e. one 16-byte
 // segment; the result quad q of a lane covers rows 8q + 4*(l/32) + (0..3).
 template <int DT, int BM, int BN, int WM, int WN, int NS, int SPR, int MF = 16>
