@@ -592,7 +592,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: inference is data-parallel with no per-forward exchange, "
-              "and this build runs on a single MI355X (see the sharding note in the design document).",
+              "so N GPUs would each run this plan on their own share of the images.",
               file=sys.stderr)
         sys.exit(2)
 
