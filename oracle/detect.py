@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 The paper evaluates Darknet's object-detection sample program (Sec. 5.1.1)
-but states no decoding rule, so the rule here is a reading (listed in the
-design notes): the output of the 9-layer network's last 1x1 conv has
+but states no decoding rule, so the rule here is a reading (Darknet's
+region-layer convention): the output of the 9-layer network's last 1x1 conv has
 ``A * (5 + C)`` channels per grid cell; for anchor ``a`` its channels
 ``a*(5+C) + (0..4)`` are the box and objectness terms ``tx, ty, tw, th, to``
 and the next ``C`` channels are class logits.  For cell (row i, column j) of
