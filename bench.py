@@ -511,6 +511,28 @@ def summarize_pmc_layers(fetch_csv: str, write_csv: str, driver_json: str, launc
     return res
 
 
+def summarize_counters(paths, launches: int = 5):
+    """Mean per dispatch of every counter over the last `launches` dispatches
+    (the dominant conv's timed launches of `bench.py --pmc-driver`) of one or
+    more rocprofv3 --pmc CSVs, with the kernel name and grid."""
+    out = {}
+    for path in paths:
+        disp = {}
+        for r in _csv_rows(path):
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                                       "vgpr": int(r["VGPR_Count"]), "agpr": int(r["Accum_VGPR_Count"]),
+                                                       "lds": int(r["LDS_Block_Size"]), "counters": {}})
+            d["counters"][r["Counter_Name"]] = d["counters"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        last = [disp[k] for k in sorted(disp)][-launches:]
+        assert len({d["kernel"] for d in last}) == 1, "last dispatches are not one kernel"
+        out.setdefault("kernel", last[0]["kernel"])
+        for key in ("grid", "vgpr", "agpr", "lds"):
+            out.setdefault(key, last[0][key])
+        for name in last[0]["counters"]:
+            out.setdefault("counters", {})[name] = float(np.mean([d["counters"][name] for d in last]))
+    return out
+
+
 def summarize_pmc(fetch_csv: str, write_csv: str, layer: int, tile: int, launches: int = 5):
     """HBM bytes per launch of the dominant conv from two rocprofv3 --pmc runs
     of `bench.py --pmc-driver` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
@@ -576,6 +598,9 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "LAYER", "TILE"),
                     help="print the HBM-traffic JSON of two --pmc-driver counter runs (the dominant conv on "
                          "tile config TILE, as the driver printed it) and exit (no GPU)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="COUNTER_CSV",
+                    help="print, per counter, the mean per dispatch over the last 5 dispatches (the dominant "
+                         "conv's launches in --pmc-driver runs) of rocprofv3 --pmc CSVs, and exit (no GPU)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
@@ -585,6 +610,9 @@ def main():
         return
     if args.summarize_api:
         print(summarize_api(args.summarize_api))
+        return
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(args.summarize_counters), indent=1))
         return
     if args.summarize_pmc:
         f, w, layer, tile = args.summarize_pmc
