@@ -384,6 +384,55 @@ __device__ __forceinline__ void splitk_tail(const ConvArgs &a, int m0, int n0)
     }
 }
 
+// Position of one lane's 16-byte K segment in the packed K order, advanced
+// K-tile by K-tile (a workgroup loads its K-tiles in increasing order): the
+// filter tap (r, s) and input channel c0 of k = kt*BKE + sc*SEG, with the
+// divisions done once at the first K-tile instead of at every one.
+// Tap-major order: k = tap*cin_p + c.  Channel-block-major (cbsh >= 0):
+// blocks of CB = 2^cbsh channels, every tap of a block before the next block;
+// a K-tile lies inside one block (BKE divides CB).  The segment is inside K
+// when r < R and c0 < cin_p.
+struct KPos {
+    int r, s, c0, off, cbase;  // off, cbase: offset in and start of the channel block
+    __device__ __forceinline__ void init(int k0, int cin_p, int RS, int S, int cbsh)
+    {
+        int tap;
+        if (cbsh < 0) {
+            tap = k0 / cin_p;
+            c0 = k0 - tap * cin_p;
+            off = cbase = 0;
+        } else {
+            const int blk = k0 >> cbsh, cb = blk / RS;
+            tap = blk - cb * RS;
+            cbase = cb << cbsh;
+            off = k0 & ((1 << cbsh) - 1);
+            c0 = cbase + off;
+        }
+        r = tap / S;
+        s = tap - r * S;
+    }
+    __device__ __forceinline__ void next(int bke, int cin_p, int R, int S, int cbsh)
+    {
+        if (cbsh < 0) {
+            c0 += bke;
+            while (c0 >= cin_p) {
+                c0 -= cin_p;
+                if (++s == S) { s = 0; ++r; }
+            }
+        } else {
+            off += bke;
+            if (off >= (1 << cbsh)) {
+                off -= 1 << cbsh;
+                if (++s == S) {
+                    s = 0;
+                    if (++r == R) { r = 0; cbase += 1 << cbsh; }
+                }
+            }
+            c0 = cbase + off;
+        }
+    }
+};
+
 template <int DT, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 {
@@ -445,6 +494,11 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
     const int RS = a.R * a.S;
     const int cbsh = kblock_ch(DT, a.cin_p, RS) == a.cin_p ? -1 : 7 - (ES >> 1);  // log2 of a 128-byte block
     const u32x4 zero4 = {0u, 0u, 0u, 0u};
+    KPos kp;
+    kp.init(kt0 * BKE + sc * SEG, a.cin_p, RS, a.S, cbsh);
+    long long a_base[AR];  // element offset of each row's tap (0, 0), channel 0 (meaningful where in range)
+#pragma unroll
+    for (int i = 0; i < AR; ++i) a_base[i] = ((long long)a_pix[i] + (long long)a_hi[i] * a.W + a_wi[i]) * a.cin_p;
 
     u32x4 ra[AR], rb[BR];
     f4 acc[FM][FN];
@@ -455,31 +509,23 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm(ConvArgs a)
 
     const int lrow = lane & 15, lgrp = lane >> 4;
 
-// Issue the global loads of K-tile KT into ra / rb (no wait).
+// Issue the global loads of K-tile KT into ra / rb (no wait).  KT must be the
+// K-tile after the previous call's (kp advances one K-tile per call).
 #define DN_GLOAD(KT)                                                                           \
     do {                                                                                       \
-        const int k0_ = (KT) * BKE + sc * SEG;                                                 \
-        int tap_, c0_;                                                                         \
-        if (cbsh < 0) {                                                                        \
-            tap_ = k0_ / a.cin_p;                                                              \
-            c0_ = k0_ - tap_ * a.cin_p;                                                        \
-        } else {                                                                               \
-            const int blk_ = k0_ >> cbsh, cb_ = blk_ / RS;                                     \
-            tap_ = blk_ - cb_ * RS;                                                            \
-            c0_ = (cb_ << cbsh) + (k0_ & ((1 << cbsh) - 1));                                   \
-        }                                                                                      \
-        const int r_ = tap_ / a.S, s_ = tap_ - (tap_ / a.S) * a.S;                             \
-        const bool kv_ = tap_ < RS && c0_ < a.cin_p;                                           \
+        const int r_ = kp.r, s_ = kp.s;                                                        \
+        const bool kv_ = r_ < a.R && kp.c0 < a.cin_p;                                          \
+        const long long toff_ = ((long long)r_ * a.W + s_) * a.cin_p + kp.c0;                  \
         _Pragma("unroll") for (int i = 0; i < AR; ++i) {                                       \
             const int hi_ = a_hi[i] + r_, wi_ = a_wi[i] + s_;                                  \
             const bool ok_ = kv_ && (unsigned)hi_ < (unsigned)a.H && (unsigned)wi_ < (unsigned)a.W; \
-            const int hh_ = ok_ ? hi_ : 0, ww_ = ok_ ? wi_ : 0;                                \
-            const size_t off_ = ((size_t)(a_pix[i] + hh_ * a.W + ww_) * a.cin_p + c0_) * ES;   \
+            const size_t off_ = ok_ ? (size_t)(a_base[i] + toff_) * ES : 0;                    \
             ra[i] = ok_ ? gload16(a.x, off_) : zero4;                                          \
         }                                                                                      \
         const size_t kb_ = (size_t)(KT) * BKE * ES;                                            \
         _Pragma("unroll") for (int i = 0; i < BR; ++i)                                         \
             rb[i] = b_ok[i] ? gload16(a.w, b_off[i] + kb_) : zero4;                            \
+        kp.next(BKE, a.cin_p, a.R, a.S, cbsh);                                                 \
     } while (0)
 
 // Write ra / rb into LDS stage BUF (rows swizzled: segment s of row r sits at s ^ (r & 7)).
@@ -680,26 +726,22 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
     const int RS = a.R * a.S;
     // channel-block-major K order uses a power-of-two block (32 / 64 / 128 channels)
     const int cbsh = kblock_ch(DT, a.cin_p, RS) == a.cin_p ? -1 : 7 - (ES >> 1);
+    KPos kp;  // this lane's K segment of the next K-tile to issue (issued in increasing order)
+    kp.init(kt0 * BKE + sc * SEG, a.cin_p, RS, a.S, cbsh);
+    long long a_base[AR];  // element offset of each row's tap (0, 0), channel 0 (meaningful where in range)
+#pragma unroll
+    for (int i = 0; i < AR; ++i) a_base[i] = ((long long)a_pix[i] + (long long)a_hi[i] * a.W + a_wi[i]) * a.cin_p;
 
     auto issue = [&](int kt, int st) {
-        const int k0 = kt * BKE + sc * SEG;
-        int tap, c0;
-        if (cbsh < 0) {
-            tap = k0 / a.cin_p;
-            c0 = k0 - tap * a.cin_p;
-        } else {
-            const int blk = k0 >> cbsh, cb = blk / RS;
-            tap = blk - cb * RS;
-            c0 = (cb << cbsh) + (k0 & ((1 << cbsh) - 1));
-        }
-        const int r = tap / a.S, s = tap - (tap / a.S) * a.S;
-        const bool kv = tap < RS && c0 < a.cin_p;
+        const int r = kp.r, s = kp.s;
+        const bool kv = r < a.R && kp.c0 < a.cin_p;
+        const long long toff = ((long long)r * a.W + s) * a.cin_p + kp.c0;
 #pragma unroll
         for (int i = 0; i < AR; ++i) {
             if (AGRP % NW != 0 && i == AR - 1 && i >= my_a) break;  // wave-uniform
             const int hi = a_hi[i] + r, wi = a_wi[i] + s;
             const bool ok = kv && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
-            const unsigned off = ok ? (unsigned)(((a_pix[i] + hi * a.W + wi) * a.cin_p + c0) * ES) : DN_OOB;
+            const unsigned off = ok ? (unsigned)((a_base[i] + toff) * ES) : DN_OOB;
             dma16(rx, off, &sA[st][(wave + i * NW) * 64]);
         }
         const unsigned kb = (unsigned)(kt * BKE * ES);
@@ -709,6 +751,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_igemm_dl(ConvArgs a)
             const unsigned off = b_off[i] == DN_OOB ? DN_OOB : b_off[i] + kb;
             dma16(rw, off, &sB[st][(wave + i * NW) * 64]);
         }
+        kp.next(BKE, a.cin_p, a.R, a.S, cbsh);
     };
 
     accT acc[FM][FN];
