@@ -156,6 +156,12 @@ __device__ __forceinline__ float activate(float v, int act, float slope)
     return v > 0.0f ? v : v * slope;
 }
 
+// The same function as one select: with lin_slope = slope for leaky and 1 for
+// linear, v > 0 ? v : v * lin_slope equals activate(v, act, slope) bit for bit
+// (for any slope; signed zeros and NaN included), without a branch on act.
+__device__ __forceinline__ float act_slope(int act, float slope) { return act == 1 ? slope : 1.0f; }
+__device__ __forceinline__ float activate_sel(float v, float lin_slope) { return v > 0.0f ? v : v * lin_slope; }
+
 // The value an output takes once stored (rounded to the storage type).
 template <int DT> __device__ __forceinline__ float stored_value(float v)
 {
@@ -872,6 +878,7 @@ __host__ __device__ constexpr int first_kstep(int dt) { return dt == FP8 ? 128 :
 int first_kpad(int dt, int R) { return (R * 16 + first_kstep(dt) - 1) / first_kstep(dt) * first_kstep(dt); }
 
 // CP floats -> one window pixel in the storage type (CP*esize bytes at dst)
+// (sc is 1 except for FP8, so only FP8 multiplies)
 template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned char *dst, const float *v, float sc)
 {
     constexpr int NW = CP * esize(DT) / 4;  // 32-bit words
@@ -879,9 +886,9 @@ template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned cha
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         if constexpr (DT == F32) {
-            w[i] = __float_as_uint(v[i] * sc);
+            w[i] = __float_as_uint(v[i]);
         } else if constexpr (DT == BF16) {
-            w[i] = (unsigned)f2bf(v[2 * i] * sc) | ((unsigned)f2bf(v[2 * i + 1] * sc) << 16);
+            w[i] = (unsigned)f2bf(v[2 * i]) | ((unsigned)f2bf(v[2 * i + 1]) << 16);
         } else {
             w[i] = (unsigned)f2e4m3(v[4 * i] * sc) | ((unsigned)f2e4m3(v[4 * i + 1] * sc) << 8) |
                    ((unsigned)f2e4m3(v[4 * i + 2] * sc) << 16) | ((unsigned)f2e4m3(v[4 * i + 3] * sc) << 24);
@@ -928,56 +935,55 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     const int KS = a.k_pad / KSTEP;
 
     // ---- stage the window: thread per pixel, PB pixels (all their channel
-    // loads) in flight per thread, (row, col) advanced incrementally
+    // loads) in flight per thread, (row, col) advanced incrementally.  The
+    // image's C planes are one buffer resource: a pixel outside the image
+    // gets an offset past its size and the channels C..CP-1 lie past it too,
+    // so both read as zero without a branch.
     {
-        constexpr int PB = 32 / CP;
+        constexpr int PB = CP == 4 ? 5 : (CP == 8 ? 3 : 2);
         const int npix = LH * LW;
-        const size_t plane = (size_t)a.H * a.W;
-        const float *xn = a.x ? a.x + (size_t)n * a.C * plane : nullptr;
-        const unsigned char *xn8 = a.x8 ? a.x8 + (size_t)n * a.C * plane : nullptr;
-        int lr = tid / LW, lc = tid % LW;
-        const int dlr = 256 / LW, dlc = 256 % LW;
-        for (int base = 0; base < npix; base += 256 * PB) {
-            float v[PB][CP];
+        const unsigned plane = (unsigned)a.H * (unsigned)a.W;
+        auto stage = [&](auto u8tag) {
+            constexpr bool U8 = decltype(u8tag)::value;
+            constexpr unsigned EB = U8 ? 1 : 4;  // bytes per input element
+            const void *img = U8 ? (const void *)(a.x8 + (size_t)n * a.C * plane) : (const void *)(a.x + (size_t)n * a.C * plane);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)img, (short)0, (int)(a.C * plane * EB), 0x00020000);
+            int lr = tid / LW, lc = tid % LW;
+            const int dlr = 256 / LW, dlc = 256 % LW;
+            for (int base = 0; base < npix; base += 256 * PB) {
+                float v[PB][CP];
 #pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                const int hi = hi0 + lr, wi = wi0 + lc;
-                const bool ok = base + j * 256 + tid < npix && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
-                const size_t o = ok ? (size_t)hi * a.W + wi : 0;
+                for (int j = 0; j < PB; ++j) {
+                    const int hi = hi0 + lr, wi = wi0 + lc;
+                    const bool ok = base + j * 256 + tid < npix && (unsigned)hi < (unsigned)a.H && (unsigned)wi < (unsigned)a.W;
+                    const unsigned off = ok ? (unsigned)(hi * a.W + wi) * EB : 0x80000000u;
 #pragma unroll
-                for (int c = 0; c < CP; ++c)
-                    v[j][c] = (ok && c < a.C) ? (xn8 ? __fdiv_rn((float)xn8[o + c * plane], 255.0f) : xn[o + c * plane]) : 0.0f;
-                lc += dlc; lr += dlr;
-                if (lc >= LW) { lc -= LW; ++lr; }
+                    for (int c = 0; c < CP; ++c) {
+                        if constexpr (U8)
+                            v[j][c] = __fdiv_rn((float)__builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, (int)(c * plane), 0), 255.0f);
+                        else
+                            v[j][c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(c * plane * 4), 0));
+                    }
+                    lc += dlc; lr += dlr;
+                    if (lc >= LW) { lc -= LW; ++lr; }
+                }
+#pragma unroll
+                for (int j = 0; j < PB; ++j) {
+                    const int p = base + j * 256 + tid;
+                    if (p < npix) put_pixel<DT, CP>(lds_raw + (size_t)p * PIXB, v[j], a.in_inv_scale);
+                }
             }
-#pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                const int p = base + j * 256 + tid;
-                if (p < npix) put_pixel<DT, CP>(lds_raw + (size_t)p * PIXB, v[j], a.in_inv_scale);
-            }
-        }
+        };
+        if (a.x8) stage(std::true_type{});
+        else stage(std::false_type{});
     }
 
     // 16 zero bytes after the window: read units past row R or tap S read here
     const int zaddr = (LH * LW * PIXB + 15) & ~15;
     if (tid == 0) *reinterpret_cast<u32x4 *>(lds_raw + zaddr) = u32x4{0u, 0u, 0u, 0u};
 
-    // ---- this lane's window offsets (bytes, relative to its pixel) for every
-    // read unit of its K segments; -1 where the unit lies past row R or tap S
-    int uoff[MAXKS][SPL][UPS];
-#pragma unroll
-    for (int ks = 0; ks < MAXKS; ++ks)
-#pragma unroll
-        for (int j = 0; j < SPL; ++j)
-#pragma unroll
-            for (int u = 0; u < UPS; ++u) {
-                const int k0 = ks * KSTEP + lgrp * KPL + j * SEG;
-                const int r = k0 / 16, rb = (k0 % 16) * ES + u * UB;  // byte within the run
-                const int s = rb / PIXB;
-                uoff[ks][j][u] = (ks < KS && r < a.R && s < a.S) ? (r * LW + s) * PIXB + rb % PIXB : -1;
-            }
-    // ---- A fragments (weights) for every 16-channel block, kept in registers
     const int nb_count = (a.cout_p + 15) / 16;
+    // ---- A fragments (weights) for every 16-channel block, kept in registers
     u32x4 aw[MAXNB][MAXKS][SPL];
 #pragma unroll
     for (int nb = 0; nb < MAXNB; ++nb)
@@ -1010,7 +1016,8 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
             scl4[nb][i] = (DT == FP8 && live) ? a.wscale[ch] * a.in_scale : ofold;
         }
     const float opost = DT == FP8 ? a.out_inv_scale : 1.0f;
-    // this image's output; offsets inside one image fit in 32 bits (checked at launch)
+    const float lsl = act_slope(a.act, a.slope);
+    // this image's output; offsets inside one image fit in 31 bits (checked at launch)
     const int Hy = POOL ? a.Ho >> 1 : a.Ho, Wy = POOL ? a.Wo >> 1 : a.Wo;
     unsigned char *yimg = reinterpret_cast<unsigned char *>(a.y) + (size_t)n * Hy * Wy * a.cout_p * ES;
     // the lane's part of its pixel position; the block's part is wave-uniform
@@ -1023,27 +1030,25 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
         lwo = lrow;
     }
     const int lpx = (lho * LW + lwo) * a.stride * PIXB;
-    int uaddr[MAXKS][SPL][UPS];  // lane pixel + unit offset, or the zero area (flagged by -1 - zaddr)
+    // ---- the read units of this lane's K segments: a unit is live inside
+    // filter row R and tap S.  Its LDS address for the block at byte offset
+    // bpx is bpx * live + ua (one 24-bit multiply-add): the block's pixel plus
+    // the lane's pixel and unit offset where live, the zero area where not.
+    int ua[MAXKS][SPL][UPS], ulive[MAXKS][SPL][UPS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
         for (int j = 0; j < SPL; ++j)
 #pragma unroll
-            for (int u = 0; u < UPS; ++u) uaddr[ks][j][u] = uoff[ks][j][u] >= 0 ? lpx + uoff[ks][j][u] : -1;
-
-    const int blocks = a.th * FT_W / 16;  // 16-pixel MFMA blocks per tile
-    for (int b = wave; b < blocks; b += 4) {
-        // wave-uniform part of the block's pixel positions
-        int bho, bwo;
-        if (POOL) {
-            bho = 2 * (b / (FT_W / 8));
-            bwo = 8 * (b % (FT_W / 8));
-        } else {
-            bho = b / (FT_W / 16);
-            bwo = (b % (FT_W / 16)) * 16;
-        }
-        const int bpx = (bho * LW + bwo) * a.stride * PIXB;
-        u32x4 bf[MAXKS][SPL];
+            for (int u = 0; u < UPS; ++u) {
+                const int k0 = ks * KSTEP + lgrp * KPL + j * SEG;
+                const int r = k0 / 16, rb = (k0 % 16) * ES + u * UB;  // byte within the run
+                const int s = rb / PIXB;
+                const bool live = ks < KS && r < a.R && s < a.S;
+                ulive[ks][j][u] = live ? 1 : 0;
+                ua[ks][j][u] = live ? lpx + (r * LW + s) * PIXB + rb % PIXB : zaddr;
+            }
+    auto read_b = [&](int bpx, u32x4 (&bf)[MAXKS][SPL]) {
 #pragma unroll
         for (int ks = 0; ks < MAXKS; ++ks)
 #pragma unroll
@@ -1051,8 +1056,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 unsigned wv[4];
 #pragma unroll
                 for (int u = 0; u < UPS; ++u) {
-                    const int ua = uaddr[ks][j][u];
-                    const unsigned char *src = lds_raw + (ua >= 0 ? bpx + ua : zaddr);
+                    const unsigned char *src = lds_raw + (__umul24((unsigned)bpx, (unsigned)ulive[ks][j][u]) + (unsigned)ua[ks][j][u]);
                     if constexpr (UB == 16) {
                         const u32x4 t = *reinterpret_cast<const u32x4 *>(src);
                         wv[0] = t.x; wv[1] = t.y; wv[2] = t.z; wv[3] = t.w;
@@ -1065,37 +1069,76 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 }
                 bf[ks][j] = u32x4{wv[0], wv[1], wv[2], wv[3]};
             }
-        // K steps past k_pad multiply zero weights by zero data: no branches
+    };
+
+    if constexpr (POOL) {
+        // Wave w takes, in every band of two output rows, the 16-pixel blocks
+        // at columns 8w and 8w + 32 (four 2x2 windows each).  Lane (lgrp,
+        // lrow) stores channel nb*16 + lrow of window lgrp: a wave-uniform
+        // offset plus a lane constant, through a buffer resource the size of
+        // the image's output, so that a window past the right edge (offset
+        // moved past the size) is dropped without a branch.
+        const __amdgpu_buffer_rsrc_t ry =
+            __builtin_amdgcn_make_buffer_rsrc((void *)yimg, (short)0, (int)((size_t)Hy * Wy * a.cout_p * ES), 0x00020000);
+        const unsigned lane_off = (unsigned)((lgrp * a.cout_p + lrow) * ES);
+        const int bands = min(a.th >> 1, Hy - (th0 >> 1));
+        for (int band = 0; band < bands; ++band) {
+            const int hp = (th0 >> 1) + band;
 #pragma unroll
-        for (int nb = 0; nb < MAXNB; ++nb) {
-            if (nb >= nb_count) break;
-            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-            if (POOL) {
-                // acc[i]: channel nb*16 + lrow of pixel 4*lgrp + i = quadrant i of window lgrp.
-                // The max is taken on the accumulators: scale > 0, bias, activation
-                // and rounding are monotone, so this equals pooling the outputs.
+            for (int hf = 0; hf < 2; ++hf) {
+                const int bwo = 8 * (wave + 4 * hf);
+                const int bpx = (2 * band * LW + bwo) * a.stride * PIXB;
+                u32x4 bf[MAXKS][SPL];
+                read_b(bpx, bf);
+                const int wpb = (tw0 >> 1) + (bwo >> 1);
+                const bool wok = wpb + lgrp < Wy;
 #pragma unroll
-                for (int ks = 0; ks < MAXKS; ++ks) mma<DT>(acc, bf[ks], aw[nb][ks]);
-                const int col = nb * 16 + lrow;
-                const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-                const float o = activate(mx * scl4[nb][0] + bias4[nb][0], a.act, a.slope) * opost;
-                const int hp = (th0 >> 1) + (bho >> 1), wp = (tw0 >> 1) + (bwo >> 1) + lgrp;
-                if (hp < Hy && col < a.cout_p && wp < Wy) {
-                    store_el<DT>(yimg, (hp * Wy + wp) * a.cout_p + col, o);
+                for (int nb = 0; nb < MAXNB; ++nb) {
+                    if (nb >= nb_count) break;
+                    // acc[i]: channel nb*16 + lrow of pixel 4*lgrp + i = quadrant i of window lgrp.
+                    // The max is taken on the accumulators: scale > 0, bias, activation
+                    // and rounding are monotone, so this equals pooling the outputs.
+                    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < MAXKS; ++ks) mma<DT>(acc, bf[ks], aw[nb][ks]);
+                    const int col = nb * 16 + lrow;
+                    const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+                    const float o = activate_sel(mx * scl4[nb][0] + bias4[nb][0], lsl) * opost;
+                    const bool ok = wok && col < a.cout_p;
+                    const int soff = ((hp * Wy + wpb) * a.cout_p + nb * 16) * ES;
+                    const int voff = ok ? (int)lane_off : (int)0x80000000u;
+                    if constexpr (DT == F32) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o), ry, voff, soff, 0);
+                    else if constexpr (DT == BF16) __builtin_amdgcn_raw_buffer_store_b16(f2bf(o), ry, voff, soff, 0);
+                    else __builtin_amdgcn_raw_buffer_store_b8(f2e4m3(o), ry, voff, soff, 0);
                     if constexpr (AM) {
-                        const float w4[4] = {acc[0], acc[1], acc[2], acc[3]};
-                        a.argmax[(size_t)n * Hy * Wy * a.cout_p + (hp * Wy + wp) * a.cout_p + col] =
-                            window_argmax<DT>(w4, scl4[nb][0], bias4[nb][0], a.act, a.slope, opost);
+                        if (ok) {
+                            const float w4[4] = {acc[0], acc[1], acc[2], acc[3]};
+                            a.argmax[(size_t)n * Hy * Wy * a.cout_p + (hp * Wy + wpb + lgrp) * a.cout_p + col] =
+                                window_argmax<DT>(w4, scl4[nb][0], bias4[nb][0], a.act, a.slope, opost);
+                        }
                     }
                 }
-            } else {
+            }
+        }
+    } else {
+        const int blocks = a.th * FT_W / 16;  // 16-pixel MFMA blocks per tile
+        for (int b = wave; b < blocks; b += 4) {
+            const int bho = b / (FT_W / 16), bwo = (b % (FT_W / 16)) * 16;
+            const int bpx = (bho * LW + bwo) * a.stride * PIXB;
+            u32x4 bf[MAXKS][SPL];
+            read_b(bpx, bf);
+            // K steps past k_pad multiply zero weights by zero data: no branches
+#pragma unroll
+            for (int nb = 0; nb < MAXNB; ++nb) {
+                if (nb >= nb_count) break;
                 // acc[i]: channel ch0 + i of this lane's pixel
+                f4 acc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < MAXKS; ++ks) mma<DT>(acc, aw[nb][ks], bf[ks]);
                 const int ch0 = nb * 16 + 4 * lgrp;
                 float v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = activate(acc[i] * scl4[nb][i] + bias4[nb][i], a.act, a.slope) * opost;
+                for (int i = 0; i < 4; ++i) v[i] = activate_sel(acc[i] * scl4[nb][i] + bias4[nb][i], lsl) * opost;
                 const int ho = th0 + bho, wo = tw0 + bwo + lrow;
                 if (ho < a.Ho && ch0 < a.cout_p && wo < a.Wo) store4<DT>(yimg, (ho * a.Wo + wo) * a.cout_p + ch0, v);
             }
@@ -1108,8 +1151,12 @@ static size_t first_lds_for(int C, int R, int S, int stride, int th, int dt)
     const int LH = (th - 1) * stride + R, LW = (FT_W - 1) * stride + S;
     return (((size_t)LH * LW * first_cp(C) * esize(dt) + 15) & ~(size_t)15) + 16;  // window + 16 zero bytes
 }
+// 32 output rows per tile where that window stays small enough for the
+// workgroups per CU the registers allow (fewer halo rows and per-tile set-up
+// per output), else 16, else 8.
 static int first_tile_h(int dt, int C, int R, int S, int stride)
 {
+    if (first_lds_for(C, R, S, stride, 32, dt) <= 20 * 1024) return 32;
     return first_lds_for(C, R, S, stride, 16, dt) <= FIRST_LDS_MAX ? 16 : 8;
 }
 size_t first_lds_bytes(int dt, int C, int R, int S, int stride)
@@ -1122,8 +1169,11 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     FirstArgs b = a;
     b.th = first_tile_h(dt, a.C, a.R, a.S, a.stride);
     const size_t lds = first_lds_for(a.C, a.R, a.S, a.stride, b.th, dt);
+    // one image's input planes (up to the padded channel count) and output
+    // are addressed through buffer resources with 31-bit offsets
     if (lds > FIRST_LDS_MAX || a.R > FIRST_MAX_R || a.C > 16 || first_cp(a.C) * a.S > 16 || a.cout_p > FIRST_MAX_COUT ||
-        a.stride > 2 || (a.cout_p & 3) || (size_t)a.Ho * a.Wo * a.cout_p >= (1u << 31))
+        a.stride > 2 || (a.cout_p & 3) || (size_t)a.Ho * a.Wo * a.cout_p * esize(dt) >= (1u << 31) ||
+        (size_t)first_cp(a.C) * a.H * a.W * 4 >= (1u << 31))
         return hipErrorInvalidValue;
     const long nblk = (long)((a.Wo + FT_W - 1) / FT_W) * ((a.Ho + b.th - 1) / b.th) * a.batch;
     if (nblk >= (1L << 31)) return hipErrorInvalidValue;
@@ -1596,6 +1646,7 @@ __global__ void __launch_bounds__(256, 2) conv_halo2(ConvArgs a, int nbuf)
     }
     const int Hp = a.Ho >> 1, Wp = a.Wo >> 1;
     const size_t img = POOL ? (size_t)Hp * Wp * a.cout_p : (size_t)a.Ho * a.Wo * a.cout_p;
+    const float lsl = act_slope(a.act, a.slope);
 
     for (int k = 0; k < my_tiles; ++k) {
         // this wave's transfers of tile k landed (loads complete in order; the
@@ -1636,6 +1687,7 @@ __global__ void __launch_bounds__(256, 2) conv_halo2(ConvArgs a, int nbuf)
         // epilogue: bias, activation, [residual], [2x2 max], round, NHWC store
         unsigned char *yimg = reinterpret_cast<unsigned char *>(a.y) + (size_t)n * img * ES;
         const unsigned char *rimg = a.res ? reinterpret_cast<const unsigned char *>(a.res) + (size_t)n * img * ES : nullptr;
+        const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc((void *)yimg, (short)0, (int)(img * ES), 0x00020000);
 #pragma unroll
         for (int nb = 0; nb < NBP; ++nb) {
             const int col = (wg * NBP + nb) * 16 + lrow;
@@ -1643,20 +1695,30 @@ __global__ void __launch_bounds__(256, 2) conv_halo2(ConvArgs a, int nbuf)
             if constexpr (POOL) {
                 // blocks i (row 2k) and i + 2 (row 2k + 1) of the same column
                 // half: lane column pairs (4*lgrp + 2j, + 1) are the windows
+                // The store offset is a wave-uniform part (window row, the
+                // block's first window) plus a lane part; a window past the
+                // right edge gets an offset past the image's output, which
+                // the buffer store drops.
 #pragma unroll
                 for (int i = 0; i < BPW; ++i) {
                     if (i & 2) continue;
                     const int hp = (th0 + h2_row(wq, NQ, i)) >> 1;
+                    if (hp >= Hp) continue;
+                    const int wpb = (tw0 + 16 * (i & 1)) >> 1;
+                    const int soff = (hp * Wp + wpb) * a.cout_p * ES;
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
                         const float w4[4] = {acc[i][nb][2 * j], acc[i][nb][2 * j + 1], acc[i + 2][nb][2 * j],
                                              acc[i + 2][nb][2 * j + 1]};
                         const float mx = fmaxf(fmaxf(w4[0], w4[1]), fmaxf(w4[2], w4[3]));
-                        const float o = activate(mx * scl[nb] + bias[nb], a.act, a.slope) * a.out_inv_scale;
-                        const int wp = ((tw0 + 16 * (i & 1)) >> 1) + 2 * lgrp + j;
-                        if (hp < Hp && wp < Wp) {
-                            store_el<DT>(yimg, (hp * Wp + wp) * a.cout_p + col, o);
-                            if constexpr (AM)
+                        const float o = activate_sel(mx * scl[nb] + bias[nb], lsl) * a.out_inv_scale;
+                        const int wp = wpb + 2 * lgrp + j;
+                        const int voff = wp < Wp ? ((2 * lgrp + j) * a.cout_p + col) * ES : (int)DN_OOB;
+                        if constexpr (DT == F32) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o), ry, voff, soff, 0);
+                        else if constexpr (DT == BF16) __builtin_amdgcn_raw_buffer_store_b16(f2bf(o), ry, voff, soff, 0);
+                        else __builtin_amdgcn_raw_buffer_store_b8(f2e4m3(o), ry, voff, soff, 0);
+                        if constexpr (AM) {
+                            if (wp < Wp)
                                 a.argmax[(size_t)n * img + (hp * Wp + wp) * a.cout_p + col] =
                                     window_argmax<DT>(w4, scl[nb], bias[nb], a.act, a.slope, a.out_inv_scale);
                         }
@@ -1672,7 +1734,7 @@ __global__ void __launch_bounds__(256, 2) conv_halo2(ConvArgs a, int nbuf)
                         const int wo = tw0 + 16 * (i & 1) + 4 * lgrp + q;
                         if (wo >= a.Wo) continue;
                         const int o = (ho * a.Wo + wo) * a.cout_p + col;
-                        float r = activate(acc[i][nb][q] * scl[nb] + bias[nb], a.act, a.slope);
+                        float r = activate_sel(acc[i][nb][q] * scl[nb] + bias[nb], lsl);
                         if (rimg) r += load_el<DT>(rimg, o) * a.res_scale;
                         store_el<DT>(yimg, o, r * a.out_inv_scale);
                     }
@@ -1709,7 +1771,7 @@ bool halo2_ok(int dt, const ConvArgs &a)
     const int ws = halo2_wslots(dt, a);
     const int nb = (a.cout_p + 15) / 16;
     return kblock_ch(dt, a.cin_p, a.R * a.S) == a.cin_p && nb <= 4 && nb != 3 && (K + kstep - 1) / kstep <= h2_ksmax(dt) &&
-           a.stride <= 2 && (size_t)a.Ho * a.Wo * a.cout_p < (1u << 31) &&
+           a.stride <= 2 && (size_t)a.Ho * a.Wo * a.cout_p * esize(dt) < (1u << 31) &&
            (size_t)a.H * a.W * a.cin_p * esize(dt) < (1u << 31) && ws / 64 <= 4 * H2_MAXBLK &&
            2 * (size_t)ws * 16 <= H2_LDS_MAX;
 }
