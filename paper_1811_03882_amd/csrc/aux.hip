@@ -149,20 +149,22 @@ hipError_t launch_ingest(int dt, const float *x, int n, int c, int h, int w, int
 
 // ---------------------------------------------------------------- egress
 // NHWC storage type -> NCHW FP32; thread per (pixel, segment), consecutive
-// threads write consecutive pixels of a channel plane.
+// threads write consecutive pixels of a channel plane.  IT is the type of the
+// thread index: 32-bit (a short division sequence) whenever the thread count
+// fits, 64-bit otherwise.
 
-template <int DT>
+template <int DT, typename IT>
 __global__ void __launch_bounds__(256) egress(const void *x, int n, int c, int hw, int cp, float scale, float *y)
 {
     constexpr int E = Seg<DT>::N;
     const int nseg = (c + E - 1) / E, cseg = cp / E;
-    const size_t total = (size_t)n * hw * nseg;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const IT total = (IT)n * hw * nseg;
+    const IT t = (IT)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int p = (int)(t % hw);
-    const size_t rest = t / hw;
-    const int sg = (int)(rest % nseg);
-    const int img = (int)(rest / nseg);
+    const int p = (int)(t % (IT)hw);
+    const IT rest = t / (IT)hw;
+    const int sg = (int)(rest % (IT)nseg);
+    const int img = (int)(rest / (IT)nseg);
     float f[E];
     Seg<DT>::dec(((const uint4 *)x)[((size_t)img * hw + p) * cseg + sg], f);
 #pragma unroll
@@ -178,12 +180,19 @@ hipError_t launch_egress(int dt, const void *x, int n, int c, int h, int w, int 
     const size_t total = (size_t)n * h * w * ((c + seg_el(dt) - 1) / seg_el(dt));
     if (total == 0) return hipSuccess;
     dim3 g((unsigned)((total + 255) / 256)), b(256);
+    const bool small = total + 256 < (1ull << 32);
+#define DN_EGRESS(D)                                                                              \
+    do {                                                                                          \
+        if (small) hipLaunchKernelGGL((egress<D, unsigned>), g, b, 0, s, x, n, c, h * w, cp, scale, y); \
+        else hipLaunchKernelGGL((egress<D, size_t>), g, b, 0, s, x, n, c, h * w, cp, scale, y);         \
+    } while (0)
     switch (dt) {
-    case F32: hipLaunchKernelGGL(egress<F32>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
-    case BF16: hipLaunchKernelGGL(egress<BF16>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
-    case FP8: hipLaunchKernelGGL(egress<FP8>, g, b, 0, s, x, n, c, h * w, cp, scale, y); break;
+    case F32: DN_EGRESS(F32); break;
+    case BF16: DN_EGRESS(BF16); break;
+    case FP8: DN_EGRESS(FP8); break;
     default: return hipErrorInvalidValue;
     }
+#undef DN_EGRESS
     return hipGetLastError();
 }
 
@@ -191,21 +200,21 @@ hipError_t launch_egress(int dt, const void *x, int n, int c, int h, int w, int 
 // -inf outside the input; window starts at i*stride - (size-1)/2.  Values are
 // decoded, compared and re-encoded, which is exact (no new values appear).
 
-template <int DT>
+template <int DT, typename IT>
 __global__ void __launch_bounds__(256) maxpool(const void *x, void *y, int n, int h, int w, int cp, int size,
                                                int stride, int ho, int wo)
 {
     constexpr int E = Seg<DT>::N;
     const int nseg = cp / E;
-    const size_t total = (size_t)n * ho * wo * nseg;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const IT total = (IT)n * ho * wo * nseg;
+    const IT t = (IT)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int sg = (int)(t % nseg);
-    const size_t p = t / nseg;
-    const int j = (int)(p % wo);
-    const size_t q = p / wo;
-    const int i = (int)(q % ho);
-    const int img = (int)(q / ho);
+    const int sg = (int)(t % (IT)nseg);
+    const size_t p = t / (IT)nseg;
+    const int j = (int)((IT)p % (IT)wo);
+    const IT q = (IT)p / (IT)wo;
+    const int i = (int)(q % (IT)ho);
+    const int img = (int)(q / (IT)ho);
     const int off = (size - 1) / 2;
     float m[E];
 #pragma unroll
@@ -231,12 +240,19 @@ hipError_t launch_maxpool(int dt, const void *x, void *y, int n, int h, int w, i
     const size_t total = (size_t)n * ho * wo * (cp / seg_el(dt));
     if (total == 0) return hipSuccess;
     dim3 g((unsigned)((total + 255) / 256)), b(256);
+    const bool small = total + 256 < (1ull << 32);
+#define DN_MAXPOOL(D)                                                                                          \
+    do {                                                                                                      \
+        if (small) hipLaunchKernelGGL((maxpool<D, unsigned>), g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); \
+        else hipLaunchKernelGGL((maxpool<D, size_t>), g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo);         \
+    } while (0)
     switch (dt) {
-    case F32: hipLaunchKernelGGL(maxpool<F32>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
-    case BF16: hipLaunchKernelGGL(maxpool<BF16>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
-    case FP8: hipLaunchKernelGGL(maxpool<FP8>, g, b, 0, s, x, y, n, h, w, cp, size, stride, ho, wo); break;
+    case F32: DN_MAXPOOL(F32); break;
+    case BF16: DN_MAXPOOL(BF16); break;
+    case FP8: DN_MAXPOOL(FP8); break;
     default: return hipErrorInvalidValue;
     }
+#undef DN_MAXPOOL
     return hipGetLastError();
 }
 
