@@ -906,6 +906,17 @@ template <int DT, int CP> __device__ __forceinline__ void put_pixel(unsigned cha
 }
 
 
+// s * v + c for a wave-uniform s (24-bit operands) as one v_mad_u32_u24.
+// Written out because, for v in {0, 1}, the compiler turns the multiply into
+// a select plus an add (two instructions).
+__device__ __forceinline__ unsigned mad_u24(int s, int v, int c)
+{
+    unsigned r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(s), "v"(v), "v"(c));
+    return r;
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
 // AM (with POOL): also store each window's argmax code (a.argmax); a template
 // flag so that the forward's own instantiations carry none of that code.
 template <int DT, bool POOL, int CP, bool AM = false>
@@ -1032,8 +1043,11 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     const int lpx = (lho * LW + lwo) * a.stride * PIXB;
     // ---- the read units of this lane's K segments: a unit is live inside
     // filter row R and tap S.  Its LDS address for the block at byte offset
-    // bpx is bpx * live + ua (one 24-bit multiply-add): the block's pixel plus
-    // the lane's pixel and unit offset where live, the zero area where not.
+    // bpx is bpx * live + ua (one 24-bit multiply-add; LDS addresses are below
+    // 2^24): the block's pixel plus the lane's pixel and unit offset where
+    // live, the zero area where not.
+    // the window's LDS address, so that a unit's address needs no further add
+    const int lds_base = (int)(unsigned)(size_t)(const __attribute__((address_space(3))) unsigned char *)lds_raw;
     int ua[MAXKS][SPL][UPS], ulive[MAXKS][SPL][UPS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks)
@@ -1046,7 +1060,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 const int s = rb / PIXB;
                 const bool live = ks < KS && r < a.R && s < a.S;
                 ulive[ks][j][u] = live ? 1 : 0;
-                ua[ks][j][u] = live ? lpx + (r * LW + s) * PIXB + rb % PIXB : zaddr;
+                ua[ks][j][u] = lds_base + (live ? lpx + (r * LW + s) * PIXB + rb % PIXB : zaddr);
             }
     auto read_b = [&](int bpx, u32x4 (&bf)[MAXKS][SPL]) {
 #pragma unroll
@@ -1056,15 +1070,15 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
                 unsigned wv[4];
 #pragma unroll
                 for (int u = 0; u < UPS; ++u) {
-                    const unsigned char *src = lds_raw + (__umul24((unsigned)bpx, (unsigned)ulive[ks][j][u]) + (unsigned)ua[ks][j][u]);
+                    const unsigned addr = mad_u24(bpx, ulive[ks][j][u], ua[ks][j][u]);
                     if constexpr (UB == 16) {
-                        const u32x4 t = *reinterpret_cast<const u32x4 *>(src);
+                        const u32x4 t = *(const __attribute__((address_space(3))) u32x4 *)(size_t)addr;
                         wv[0] = t.x; wv[1] = t.y; wv[2] = t.z; wv[3] = t.w;
                     } else if constexpr (UB == 8) {
-                        const uint2 t = *reinterpret_cast<const uint2 *>(src);
+                        const u32x2 t = *(const __attribute__((address_space(3))) u32x2 *)(size_t)addr;
                         wv[2 * u] = t.x; wv[2 * u + 1] = t.y;
                     } else {
-                        wv[u] = *reinterpret_cast<const unsigned *>(src);
+                        wv[u] = *(const __attribute__((address_space(3))) unsigned *)(size_t)addr;
                     }
                 }
                 bf[ks][j] = u32x4{wv[0], wv[1], wv[2], wv[3]};
