@@ -119,6 +119,7 @@ FIRST = [
     (1, 21, 70, 6, 16, 2, 1, 0, 0),     # 6 channels padded to 8, 2x2 filter, ragged columns
     (2, 17, 66, 16, 24, 1, 2, 0, 0),    # 16 channels, 1x1 stride 2
     (1, 33, 40, 1, 64, 4, 2, 1, 0),     # 1 channel, 4x4 stride 2, 4 channel blocks
+    (2, 70, 100, 3, 16, 3, 1, 1, 1),    # pooled, 32-row tiles: 3 tile rows (the last 6 rows), ragged columns
 ]
 
 
