@@ -1570,18 +1570,22 @@ static void save_tune_cache(const dn_net *net)
 }
 
 // The tuned choice: the fastest candidate, except that candidates within
-// TUNE_TIE of it count as tied and the tie goes to the first in a fixed order
+// `tie` of it count as tied and the tie goes to the first in a fixed order
 // (fewest splits, then lowest config index), so that two configurations whose
-// timings differ by run-to-run noise do not trade places between runs.
-constexpr float TUNE_TIE = 0.03f;
-static void pick_tuned(const std::vector<std::tuple<float, int, int>> &timed, int *tile, int *splits)
+// timings differ by run-to-run noise do not trade places between runs.  The
+// candidates within TUNE_TIE of the fastest in the first, short timing are
+// timed again, longer and interleaved, and the pick among them uses the
+// narrower TUNE_TIE_FINE.
+constexpr float TUNE_TIE = 0.03f, TUNE_TIE_FINE = 0.01f;
+static void pick_tuned(const std::vector<std::tuple<float, int, int>> &timed, int *tile, int *splits,
+                       float tie = TUNE_TIE)
 {
     if (timed.empty()) return;
     float best = 1e30f;
     for (const auto &c : timed) best = std::min(best, std::get<0>(c));
     bool have = false;
     for (const auto &c : timed) {
-        if (std::get<0>(c) > best * (1.0f + TUNE_TIE)) continue;
+        if (std::get<0>(c) > best * (1.0f + tie)) continue;
         const int t = std::get<1>(c), sp = std::get<2>(c);
         if (!have || sp < *splits || (sp == *splits && t < *tile)) {
             *tile = t;
@@ -1626,6 +1630,16 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
         const int M = batch * (op.pool ? op.Ho * 2 : op.Ho) * (op.pool ? op.Wo * 2 : op.Wo);
         const int nkt = net->cw[op.conv].k_pad / bk_el(p.dtype);
         std::vector<std::tuple<float, int, int>> timed;  // (ms, tile, splits)
+        // mean time of `iters` back-to-back launches of one configuration
+        auto time_cfg = [&](int t, int sp, int iters) -> float {
+            float ms = 0.f;
+            if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event");
+            for (int it = 0; it < iters && rc == DN_OK; ++it) rc = enqueue_op(net, p, op, base, s, false, t, sp);
+            if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = fail(DN_EHIP, "tuning launch failed: %s", hipGetErrorString(hipGetLastError()));
+            if (rc == DN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+            return ms / iters;
+        };
         std::vector<int> cands;
         if (op_halo_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO_TILE);
         if (op_halo2_ok(net, p.dtype, op, net->cw[op.conv].k_pad)) cands.push_back(HALO2_TILE);
@@ -1643,23 +1657,37 @@ extern "C" dn_status dn_autotune(dn_net *net, int batch, int h, int w, void *str
                 const size_t need = sp > 1 ? (size_t)sp * M * op.cout_p * 4 : 0;
                 if (p.ws_off + need > net->arena_bytes) continue;
                 float ms = 0.f;
-                for (int rep = 0; rep < 2 && rc == DN_OK; ++rep) {  // rep 0 = warm-up
-                    const int iters = rep ? 5 : 1;
-                    if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DN_EHIP, "event");
-                    for (int it = 0; it < iters && rc == DN_OK; ++it) rc = enqueue_op(net, p, op, base, s, false, t, sp);
-                    if (rc == DN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                        rc = fail(DN_EHIP, "tuning launch failed: %s", hipGetErrorString(hipGetLastError()));
-                    if (rc == DN_OK && rep) {
-                        (void)hipEventElapsedTime(&ms, e0, e1);
-                        ms /= iters;
-                    }
-                }
+                for (int rep = 0; rep < 2 && rc == DN_OK; ++rep)  // rep 0 = warm-up
+                    ms = time_cfg(t, sp, rep ? 5 : 1);
                 if (rc == DN_OK) timed.emplace_back(ms, t, sp);
             }
         }
         if (rc != DN_OK) break;
+        // the near-ties again: three rounds of 20 launches each, round-robin
+        // over the candidates so that a clock change affects them alike; each
+        // keeps the median of its rounds
+        float best = 1e30f;
+        for (const auto &c : timed) best = std::min(best, std::get<0>(c));
+        std::vector<size_t> near;
+        for (size_t i = 0; i < timed.size(); ++i)
+            if (std::get<0>(timed[i]) <= best * (1.0f + TUNE_TIE)) near.push_back(i);
+        if (near.size() > 1) {
+            std::vector<std::vector<float>> rounds(near.size());
+            for (int r = 0; r < 3 && rc == DN_OK; ++r)
+                for (size_t k = 0; k < near.size() && rc == DN_OK; ++k) {
+                    const auto &c = timed[near[k]];
+                    rounds[k].push_back(time_cfg(std::get<1>(c), std::get<2>(c), 20));
+                }
+            if (rc != DN_OK) break;
+            std::vector<std::tuple<float, int, int>> fine;
+            for (size_t k = 0; k < near.size(); ++k) {
+                std::sort(rounds[k].begin(), rounds[k].end());
+                fine.emplace_back(rounds[k][1], std::get<1>(timed[near[k]]), std::get<2>(timed[near[k]]));
+            }
+            timed.swap(fine);
+        }
         int bt = op.tile, bs = op.splits;
-        pick_tuned(timed, &bt, &bs);
+        pick_tuned(timed, &bt, &bs, near.size() > 1 ? TUNE_TIE_FINE : TUNE_TIE);
         std::lock_guard<std::mutex> g(net->mu);
         net->tuned[sig] = {bt, bs};
     }
