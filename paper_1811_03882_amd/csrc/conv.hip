@@ -919,7 +919,7 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 // AM (with POOL): also store each window's argmax code (a.argmax); a template
 // flag so that the forward's own instantiations carry none of that code.
-template <int DT, bool POOL, int CP, bool AM = false>
+template <int DT, bool POOL, int CP, bool AM = false, int NBM = FIRST_MAX_COUT / 16>
 __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
 {
     constexpr int ES = esize(DT), SEG = seg_el(DT);
@@ -929,7 +929,7 @@ __global__ void __launch_bounds__(256) conv_first(FirstArgs a)
     constexpr int UB = PIXB < 16 ? PIXB : 16;                    // LDS read unit
     constexpr int UPS = 16 / UB;                                 // read units per 16-byte segment
     constexpr int MAXKS = DT == FP8 ? 1 : (DT == BF16 ? 2 : 4);  // K-steps for R <= FIRST_MAX_R
-    constexpr int MAXNB = FIRST_MAX_COUT / 16;
+    constexpr int MAXNB = NBM;  // 16-channel output blocks this instance handles at most
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int LH = (a.th - 1) * a.stride + a.R, LW = (FT_W - 1) * a.stride + a.S;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1194,8 +1194,13 @@ hipError_t launch_conv_first(int dt, const FirstArgs &a, hipStream_t s)
     dim3 grid((unsigned)nblk);
 #define DN_FIRST_CP(D, P, C, M)                                                                      \
     do {                                                                                             \
-        allow_lds(conv_first<D, P, C, M>, lds);                                                      \
-        hipLaunchKernelGGL((conv_first<D, P, C, M>), grid, dim3(256), lds, s, b);                    \
+        if (b.cout_p <= 16) {                                                                        \
+            allow_lds(conv_first<D, P, C, M, 1>, lds);                                               \
+            hipLaunchKernelGGL((conv_first<D, P, C, M, 1>), grid, dim3(256), lds, s, b);             \
+        } else {                                                                                     \
+            allow_lds(conv_first<D, P, C, M>, lds);                                                  \
+            hipLaunchKernelGGL((conv_first<D, P, C, M>), grid, dim3(256), lds, s, b);                \
+        }                                                                                            \
     } while (0)
 #define DN_FIRST_P(D, P, M)                                                                          \
     do {                                                                                             \
